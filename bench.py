@@ -1,0 +1,193 @@
+#!/usr/bin/env python3
+"""Renderer benchmark: Gsamples/s and ms/frame for 1024x1024 perspective views of
+the 512x512x1024 float32 noisy spectral cube (noise sigma 1 plus 200 Gaussian
+sources), trilinear sampling, step 0.5 voxel, ramp transfer function clipped
+below 3 sigma, emission-absorption compositing with early termination at 0.99,
+32^3 bricks with 8^3-cell empty-space skipping.
+
+One step = one frame: the whole hot path (ray set-up, brick traversal, skip
+tests, sampling, classification, compositing, store) for one orbit view; the
+16 seeded views are cycled.  Inputs are resident in HBM before timing starts.
+Prints ONE JSON line.  Only one GPU is supported.
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_HBM_GBS = 8000.0          # MI355X HBM3E
+PEAK_FP32_VECTOR_TFLOPS = 157.3  # MI355X fp32 vector (packed-FMA figure)
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def cpu_threads():
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    return max(1, min(n, 16))
+
+
+def cpu_baseline(vol, tf, wl, cams, W, H, mode, budget_s=12.0, max_views=4):
+    """The FP64 reference timed on the host cores over whole frames until ~budget_s."""
+    import numpy as np
+
+    import oracle
+    th = cpu_threads()
+    total, t_all, nviews = 0, 0.0, 0
+    for cam in cams[:max_views]:
+        t0 = time.perf_counter()
+        res = oracle.render(vol, mode=oracle.EA if mode == "ea" else oracle.MIP,
+                            tf=tf.astype(np.float64), v0=wl.v0, v1=wl.v1, clip=wl.clip_k,
+                            step=wl.step, ert=float(np.float32(wl.ert)), camera=cam, width=W,
+                            height=H, threads=th)
+        t_all += time.perf_counter() - t0
+        total += int(res["n_nominal"].sum())
+        nviews += 1
+        if t_all >= budget_s:
+            break
+    return {"value": total / t_all / 1e9, "unit": "Gsamples/s", "cores": th, "kind": "oracle",
+            "sample": "%d full %dx%d frame(s) of the same workload (views 0..%d), %.1f s"
+                      % (nviews, W, H, nviews - 1, t_all)}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=48)
+    ap.add_argument("--warmup", type=int, default=4)
+    ap.add_argument("--mode", default="ea", choices=["ea", "mip"])
+    ap.add_argument("--storage", default="f32", choices=["f32", "f16", "bf16"])
+    ap.add_argument("--size", type=int, default=1024, help="image width = height")
+    ap.add_argument("--no-skip", action="store_true")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only (--gpus %d requested); the renderer has no "
+              "multi-GPU path in this build" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_1001_2049_amd import Renderer
+
+    wl = synth.full()
+    W = H = args.size
+    log("generating %dx%dx%d cube" % (wl.cube.nx, wl.cube.ny, wl.cube.nz))
+    vol = synth.cube(wl.cube, threads=cpu_threads())
+    tf = synth.ramp_tf(256, wl.kappa_max)
+    cams = [synth.orbit_camera(wl.cube.nx, wl.cube.ny, wl.cube.nz, th, ph)
+            for th, ph in synth.orbit_angles(wl.extra["camera_seed"], wl.extra["n_views"])]
+
+    r = Renderer(0)
+    t0 = time.perf_counter()
+    cube = r.upload(vol, args.storage)
+    log("upload %.3f s" % (time.perf_counter() - t0))
+    r.set_transfer_function(tf, wl.v0, wl.v1)
+    r.set_noise_clip(wl.clip_k, wl.cube.sigma)
+    out = r.output(W, H, args.mode)
+    kw = dict(mode=args.mode, step=wl.step, ert=wl.ert, use_skip=not args.no_skip, out=out)
+
+    # per-view sample counts (untimed pass with counters)
+    nominal, executed = [], []
+    for cam in cams:
+        r.set_camera(cam)
+        _, st = r.render(cube, W, H, stats=True, **kw)
+        nominal.append(st["samples_nominal"])
+        executed.append(st["samples_exec"])
+    log("nominal samples/frame: mean %.4g" % np.mean(nominal))
+
+    stream = torch.cuda.current_stream()
+    for k in range(args.warmup):
+        r.set_camera(cams[k % len(cams)])
+        r.render(cube, W, H, **kw)
+    torch.cuda.synchronize()
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+           for _ in range(args.steps)]
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        r.set_camera(cams[k % len(cams)])
+        evs[k][0].record(stream)
+        r.render(cube, W, H, **kw)
+        evs[k][1].record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    kernel_ms = [a.elapsed_time(b) for a, b in evs]
+    samples = sum(nominal[k % len(cams)] for k in range(args.steps))
+    samples_exec = sum(executed[k % len(cams)] for k in range(args.steps))
+    gsps = samples / wall / 1e9
+    avg_ms = float(np.mean(kernel_ms))
+
+    elem = {"f32": 4, "f16": 2, "bf16": 2}[args.storage]
+    cube_bytes = wl.cube.nx * wl.cube.ny * wl.cube.nz * elem
+    img_bytes = W * H * (16 if args.mode == "ea" else 4)
+    alg_bytes = cube_bytes + img_bytes
+    achieved = alg_bytes / (avg_ms * 1e-3) / 1e9
+    flops_per_sample = 40 if args.mode == "ea" else 20
+    alu_achieved = samples / args.steps * flops_per_sample / (avg_ms * 1e-3) / 1e12
+
+    res = {
+        "metric": "Gsamples/s (nominal samples per second), 1024x1024 view of 512x512x1024 cube",
+        "value": round(gsps, 3),
+        "unit": "Gsamples/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(wall / args.steps * 1e3, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": args.storage,
+        "data": "synthetic (seeded noise + 200 Gaussian sources)",
+        "config": {
+            "workload": "full-512x512x1024 %s cube, %dx%d perspective orbit views (16 seeded), "
+                        "%s trilinear, step 0.5, ERT 0.99, ramp TF [3,50] clipped at 3 sigma, "
+                        "32^3 bricks, 8^3 skip cells%s" % (args.storage, W, H, args.mode.upper(),
+                                                          "" if not args.no_skip else ", skip off"),
+            "image": [W, H],
+            "cube": [wl.cube.nx, wl.cube.ny, wl.cube.nz],
+            "mode": args.mode,
+            "samples_per_frame": float(np.mean(nominal)),
+            "executed_samples_per_frame": float(samples_exec / args.steps),
+            "kernel_ms_mean": round(avg_ms, 4),
+            "kernel_ms_median": round(float(np.median(kernel_ms)), 4),
+            "kernel_ms_p90": round(float(np.percentile(kernel_ms, 90)), 4),
+        },
+        "roofline": {
+            "bound": "hbm",
+            "achieved": round(achieved, 1),
+            "peak": PEAK_HBM_GBS,
+            "unit": "GB/s",
+            "frac": round(achieved / PEAK_HBM_GBS, 4),
+            "traffic": None,
+            "kernel": "k_render<%s,%s,trilinear>" % (args.mode, args.storage),
+            "algorithmic_bytes_per_launch": alg_bytes,
+        },
+        "alu_roofline": {
+            "bound": "alu",
+            "achieved": round(alu_achieved, 2),
+            "peak": PEAK_FP32_VECTOR_TFLOPS,
+            "unit": "TFLOP/s",
+            "frac": round(alu_achieved / PEAK_FP32_VECTOR_TFLOPS, 4),
+            "flops_per_sample": flops_per_sample,
+        },
+    }
+    if not args.no_cpu_baseline:
+        log("timing the CPU reference")
+        res["cpu_baseline"] = cpu_baseline(vol, tf, wl, cams, W, H, args.mode)
+    r.close()
+    print(json.dumps(res), flush=True)
+
+
+if __name__ == "__main__":
+    main()

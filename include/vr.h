@@ -1,0 +1,263 @@
+/*
+ * vr.h — C interface of the MI355X volume renderer for noisy spectral cubes.
+ *
+ * The renderer casts one ray per output pixel through an (x, y, frequency)
+ * data cube and maps each pixel to RGBA through a pre-selected transfer
+ * function (paper Sec. 3, "Framework Modules", process step 3; ray casting is
+ * design decision 1 of Sec. 2).  Samples are trilinear (or nearest), values
+ * below a noise clip k*sigma are treated as empty (the paper's attention to
+ * low signal-to-noise data, abstract), and samples are composited front to
+ * back under the emission-absorption model with early ray termination, or
+ * reduced by maximum-intensity projection.  The calls below follow the
+ * paper's thin-client model: the user turns interaction into rendering
+ * commands (Fig. 1 caption): upload a cube, set the transfer function and
+ * noise clip, set the camera, render.
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ *  * Cube layout: voxel (x, y, z) of an nx*ny*nz cube lives at linear index
+ *    (z*ny + y)*nx + x (x fastest; a stack of channel images).  Voxel centres
+ *    sit at integer coordinates, unit spacing; the cube occupies
+ *    [-1/2, n-1/2] on each axis.  Samples outside [0, n-1] clamp to the edge.
+ *  * Pixels: column i left to right, row j top to bottom; an image is stored
+ *    row-major, [height][width][4] float32 premultiplied RGBA (emission-
+ *    absorption) or [height][width] float32 (MIP, data units; -inf where the
+ *    ray misses the cube, 0 where the maximum is below the clip).
+ *  * Perspective ray for pixel (i,j): f = |target-eye|, r = |f x up|,
+ *    u = r x f, h = tan(fovy/2), a = width/height,
+ *    d = |f + (2(i+1/2)/W - 1) h a r + (1 - 2(j+1/2)/H) h u|, origin eye,
+ *    sampled for t >= 0.  Orthographic: d = f, origin target + ((i+1/2)/W -
+ *    1/2) ortho_w r + (1/2 - (j+1/2)/H) ortho_h u; the whole line is sampled.
+ *  * Sample lattice: with [t_in, t_out] the ray's chord through the cube and
+ *    L its length, n = ceil(L/step) segments of length step (the last one
+ *    shorter), each sampled at its midpoint.
+ *  * Transfer function: n >= 2 rows (r, g, b, kappa), kappa an extinction
+ *    coefficient per voxel length, spread evenly over [v0, v1] in data units
+ *    and interpolated linearly (clamped outside).  A sample value v below the
+ *    clip c contributes nothing.  Per segment alpha = 1 - exp(-kappa len);
+ *    C += T alpha rgb; T *= 1 - alpha; the ray stops once 1 - T >= ert_alpha.
+ *
+ * Ownership and threading
+ * -----------------------
+ *  * The library owns brick pools, statistics, skip masks and transfer-
+ *    function tables.  They are allocated through the optional allocator
+ *    given to vr_create (e.g. a framework's caching allocator), otherwise
+ *    with hipMalloc.  Callers own every buffer they pass in.
+ *  * Device pointers passed in (out_dev, device-resident sources) must be
+ *    valid on the context's device; hip_stream arguments are hipStream_t
+ *    values (NULL = the default stream).
+ *  * Calls on one context are serialised by an internal mutex; a context may
+ *    be used from several threads.
+ *  * vr_render snapshots the context's transfer function, clip and camera at
+ *    call time; later set_* calls never affect work already enqueued.
+ *
+ * Errors
+ * ------
+ *  Every call returns a vr_status; no C++ exception or abort crosses this
+ *  interface.  Arguments are validated before any device call.  On failure
+ *  vr_last_error() describes the most recent error of the calling thread.
+ *  An asynchronous device fault is reported as VR_EDEVICE by the next call
+ *  that synchronises; the context must then be destroyed.
+ */
+#ifndef VR_H
+#define VR_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct vr_ctx_s* vr_ctx;
+typedef int32_t vr_cube;   /* cube handle, > 0; stale handles give VR_ENOTFOUND */
+typedef int32_t vr_tf;     /* transfer-function handle, > 0 */
+typedef int32_t vr_status;
+
+enum {
+    VR_OK = 0,
+    VR_EINVAL = -1,       /* invalid argument (nothing was changed) */
+    VR_ENOMEM = -2,       /* device memory or the context's budget is exhausted */
+    VR_ENOTFOUND = -3,    /* unknown or released handle */
+    VR_EBUSY = -4,        /* object in use by queued work */
+    VR_EDEVICE = -5,      /* HIP error, or a host-only context asked for device work */
+    VR_EUNSUPPORTED = -6, /* valid but not supported combination */
+    VR_ESTATE = -7        /* a required piece of state (camera, transfer function) is unset */
+};
+
+enum { VR_F32 = 0, VR_F16 = 1, VR_BF16 = 2 };         /* voxel storage formats */
+enum { VR_EA = 0, VR_MIP = 1 };                       /* render modes */
+enum { VR_NEAREST = 0, VR_TRILINEAR = 1 };            /* interpolation */
+
+/* Optional device allocator.  alloc returns device memory of at least
+ * `bytes` bytes (256-byte aligned) or NULL; free releases it.  Both may be
+ * called from any thread that calls into the library. */
+typedef struct {
+    void* (*alloc)(uint64_t bytes, void* user);
+    void (*free)(void* ptr, uint64_t bytes, void* user);
+    void* user;
+} vr_allocator;
+
+typedef struct {
+    int32_t ortho;              /* 0 perspective, 1 orthographic */
+    int32_t reserved;
+    double eye[3];              /* voxel coordinates */
+    double target[3];
+    double up[3];               /* must not be parallel to target - eye */
+    double fovy_deg;            /* perspective: vertical field of view, (0, 180) */
+    double ortho_w, ortho_h;    /* orthographic: window size in voxels, > 0 */
+} vr_camera;
+
+typedef struct {
+    int32_t mode;               /* VR_EA or VR_MIP */
+    int32_t interp;             /* VR_NEAREST or VR_TRILINEAR */
+    float step;                 /* lattice spacing along rays in voxels, > 0 */
+    float ert_alpha;            /* early termination opacity in (0, 1]; > 1 disables */
+    int32_t width, height;      /* 1 .. 16384 */
+    int32_t use_skip;           /* 1: skip empty space (never changes the image), 0: off */
+    int32_t reserved;
+} vr_render_params;
+
+typedef struct {
+    uint64_t samples_nominal;   /* sum over pixels of the lattice size n */
+    uint64_t samples_exec;      /* samples actually interpolated */
+    uint64_t rays_hit;          /* rays that intersect the cube */
+    uint64_t rays_ert;          /* rays stopped by early termination */
+    uint64_t cells_skipped;     /* empty cells jumped over */
+    float kernel_ms;            /* device time of the render kernel */
+    float reserved;
+} vr_stats;
+
+typedef struct {
+    int64_t nx, ny, nz;
+    int32_t storage;            /* VR_F32 / VR_F16 / VR_BF16 */
+    int32_t brick;              /* brick edge in voxels (32) */
+    int32_t bricks_x, bricks_y, bricks_z;
+    int32_t cell;               /* skip-cell edge in voxels (8) */
+    double sigma_scale;         /* stored value = value / sigma_scale */
+    uint64_t pool_bytes;        /* device bytes of the brick pool */
+    uint64_t brick_stride;      /* bytes between brick slots */
+    uint64_t aux_bytes;         /* device bytes of tables and statistics */
+    float vmin, vmax;           /* range of stored values times sigma_scale */
+    /* device pointers, for inspection: */
+    const void* pool;           /* brick slots, each (brick+1)^3 values, x fastest */
+    const uint32_t* slot_of_brick; /* [bricks_z][bricks_y][bricks_x] -> slot */
+    const float* cell_minmax;   /* per slot: 64 cells x (min, max) of stored values */
+} vr_cube_info;
+
+/* --- context ------------------------------------------------------------ */
+
+/* Create a context on HIP device `device`.  hbm_budget_bytes caps the device
+ * memory the context's cubes may hold (0 = no cap).  device = -1 creates a
+ * host-only context that validates arguments and keeps state but rejects
+ * device work with VR_EDEVICE.  alloc may be NULL. */
+vr_status vr_create(int32_t device, uint64_t hbm_budget_bytes, const vr_allocator* alloc,
+                    vr_ctx* out);
+
+/* Destroy a context, its cubes, tables and server.  Waits for queued work. */
+vr_status vr_destroy(vr_ctx ctx);
+
+/* Text of the calling thread's most recent error; valid until its next call. */
+const char* vr_last_error(void);
+
+/* Library version string. */
+const char* vr_version(void);
+
+/* --- cubes ---------------------------------------------------------------- */
+
+/* Upload an nx*ny*nz cube (each >= 2).  src holds values of type src_dtype
+ * (VR_F32, or codes of VR_F16/VR_BF16 that are stored as-is and then require
+ * storage == src_dtype), in host memory (src_on_device = 0) or device memory
+ * (1).  Float32 sources are converted to `storage` as round-to-nearest-even
+ * of value/sigma_scale.  The cube is re-laid out into 32^3 bricks with a one-
+ * voxel apron (Morton-ordered slots) and per-8^3-cell min/max tables
+ * (paper Sec. 3 process step 1: the cube is partitioned into sub-cubes).
+ * Returns after src may be reused; the cube is ready for work on any stream
+ * once this call returns. */
+vr_status vr_cube_upload(vr_ctx ctx, const void* src, int32_t src_dtype, int32_t src_on_device,
+                         int64_t nx, int64_t ny, int64_t nz, int32_t storage, double sigma_scale,
+                         void* hip_stream, vr_cube* out);
+
+/* Release a cube.  VR_EBUSY if queued serving requests still reference it. */
+vr_status vr_cube_release(vr_ctx ctx, vr_cube cube);
+
+/* Describe a cube (sizes, layout, device pointers for inspection). */
+vr_status vr_cube_get_info(vr_ctx ctx, vr_cube cube, vr_cube_info* out);
+
+/* --- transfer function, clip, camera --------------------------------------- */
+
+/* Set the context's transfer function: rgbk holds n rows (r, g, b, kappa),
+ * n in [2, 4096], finite, kappa >= 0, spread over [v0, v1] (v1 > v0, data
+ * units).  The table is copied. */
+vr_status vr_set_transfer_function(vr_ctx ctx, const float* rgbk, int32_t n, float v0, float v1);
+
+/* Set the noise clip c = k * sigma (data units).  k = -inf disables it.
+ * sigma > 0 and finite. */
+vr_status vr_set_noise_clip(vr_ctx ctx, float k, float sigma);
+
+/* Set the camera (validated: finite, up not parallel to the view direction,
+ * perspective fovy in (0, 180), orthographic window > 0). */
+vr_status vr_set_camera(vr_ctx ctx, const vr_camera* cam);
+
+/* --- rendering ----------------------------------------------------------- */
+
+/* Render `cube` with the context's current state into out_dev (device
+ * memory of width*height*4 floats for VR_EA, width*height floats for
+ * VR_MIP), enqueued on hip_stream.  With stats != NULL the call waits for
+ * the render and fills the counters; otherwise it returns once enqueued.
+ * VR_ESTATE if the camera (or, for VR_EA, the transfer function) is unset. */
+vr_status vr_render(vr_ctx ctx, vr_cube cube, const vr_render_params* params, void* out_dev,
+                    void* hip_stream, vr_stats* stats);
+
+/* --- batched rendering and serving ---------------------------------------- */
+
+/* Transfer functions as objects, for requests that carry their own. */
+vr_status vr_tf_create(vr_ctx ctx, const float* rgbk, int32_t n, float v0, float v1, vr_tf* out);
+vr_status vr_tf_release(vr_ctx ctx, vr_tf tf);
+
+/* One view request.  tf = 0 uses the context's current transfer function;
+ * clip is in data units (-inf: none). */
+typedef struct {
+    vr_cube cube;
+    vr_tf tf;
+    float clip;
+    int32_t reserved;
+    vr_camera camera;
+    vr_render_params params;
+    void* out_dev;              /* as for vr_render */
+} vr_request;
+
+/* Render `count` requests (up to 4096; any mix of cubes, sizes, modes) in one
+ * persistent launch on hip_stream.  Each image equals what the request gives
+ * when rendered alone in a batch of one.  Optional per-request stats as in
+ * vr_render (the call then waits). */
+vr_status vr_render_batch(vr_ctx ctx, const vr_request* reqs, int32_t count, void* hip_stream,
+                          vr_stats* stats);
+
+typedef struct {
+    int32_t max_batch_requests; /* requests admitted per launch (1..4096) */
+    int32_t max_batch_tiles;    /* 16x16-pixel tiles per launch (>= 1) */
+    int32_t max_inflight;       /* launches in flight (1..4) */
+    int32_t use_graphs;         /* 1: replay a captured graph per shape class */
+} vr_server_cfg;
+
+/* Start/stop the serving loop (a host thread owned by the context). */
+vr_status vr_server_start(vr_ctx ctx, const vr_server_cfg* cfg);
+vr_status vr_server_stop(vr_ctx ctx);
+
+/* Queue a request; returns a ticket.  Requests that arrive while others are
+ * on the device join the next launch (continuous batching). */
+vr_status vr_submit(vr_ctx ctx, const vr_request* req, uint64_t* ticket);
+
+/* done = 1 once the ticket's image is complete in out_dev. */
+vr_status vr_poll(vr_ctx ctx, uint64_t ticket, int32_t* done);
+
+/* Wait for a ticket (timeout_s <= 0: forever).  latency_s (nullable) gets
+ * completion time minus submission time as measured by the server. */
+vr_status vr_wait(vr_ctx ctx, uint64_t ticket, double timeout_s, double* latency_s);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* VR_H */

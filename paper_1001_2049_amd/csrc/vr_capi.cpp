@@ -1,0 +1,1143 @@
+// vr_capi.cpp — the C interface: context, validation, cube upload (bricking),
+// transfer functions, skip classification cache, single and batched renders.
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <numeric>
+
+#include "vr_host.h"
+#include "vr_launch.h"
+#include "vr_server.h"
+
+namespace vrh {
+
+static thread_local std::string g_err;
+
+void set_error(const std::string& msg) { g_err = msg; }
+
+vr_status hip_check(hipError_t e, const char* what) {
+    if (e == hipSuccess) return VR_OK;
+    set_error(std::string(what) + ": " + hipGetErrorString(e));
+    return VR_EDEVICE;
+}
+
+uint64_t Cube::bytes() const {
+    uint64_t b = pool.bytes + slots.bytes + cellmm.bytes;
+    for (const auto& m : masks) b += m.buf.bytes;
+    return b;
+}
+
+vr_status dev_alloc(Ctx* c, DevBuf& b, uint64_t bytes, bool budgeted) {
+    if (bytes == 0) bytes = 256;
+    bytes = (bytes + 255) & ~uint64_t(255);
+    if (budgeted && c->budget && c->used + bytes > c->budget) {
+        set_error("device memory budget exceeded (" + std::to_string(c->used + bytes) + " > " +
+                  std::to_string(c->budget) + " bytes)");
+        return VR_ENOMEM;
+    }
+    void* p = nullptr;
+    if (c->has_alloc) {
+        p = c->alloc.alloc(bytes, c->alloc.user);
+        if (!p) {
+            set_error("allocator returned NULL for " + std::to_string(bytes) + " bytes");
+            return VR_ENOMEM;
+        }
+    } else {
+        hipError_t e = hipMalloc(&p, bytes);
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            set_error(std::string("hipMalloc: ") + hipGetErrorString(e));
+            return VR_ENOMEM;
+        }
+    }
+    b.ptr = p;
+    b.bytes = bytes;
+    if (budgeted) c->used += bytes;
+    return VR_OK;
+}
+
+void dev_free(Ctx* c, DevBuf& b, bool budgeted) {
+    if (!b.ptr) return;
+    if (c->has_alloc) c->alloc.free(b.ptr, b.bytes, c->alloc.user);
+    else (void)hipFree(b.ptr);
+    if (budgeted) c->used -= b.bytes;
+    b = DevBuf{};
+}
+
+static bool finite3(const double* v) {
+    return std::isfinite(v[0]) && std::isfinite(v[1]) && std::isfinite(v[2]);
+}
+
+vr_status check_camera(const vr_camera* cam) {
+    if (!cam) {
+        set_error("camera is NULL");
+        return VR_EINVAL;
+    }
+    if (!finite3(cam->eye) || !finite3(cam->target) || !finite3(cam->up)) {
+        set_error("camera vectors must be finite");
+        return VR_EINVAL;
+    }
+    double f[3] = {cam->target[0] - cam->eye[0], cam->target[1] - cam->eye[1],
+                   cam->target[2] - cam->eye[2]};
+    double fl = std::sqrt(f[0] * f[0] + f[1] * f[1] + f[2] * f[2]);
+    double ul = std::sqrt(cam->up[0] * cam->up[0] + cam->up[1] * cam->up[1] +
+                          cam->up[2] * cam->up[2]);
+    if (!(fl > 0.0) || !(ul > 0.0)) {
+        set_error("camera: eye == target or zero up vector");
+        return VR_EINVAL;
+    }
+    double r[3] = {f[1] * cam->up[2] - f[2] * cam->up[1], f[2] * cam->up[0] - f[0] * cam->up[2],
+                   f[0] * cam->up[1] - f[1] * cam->up[0]};
+    double rl = std::sqrt(r[0] * r[0] + r[1] * r[1] + r[2] * r[2]);
+    if (!(rl > 1e-9 * fl * ul)) {
+        set_error("camera: up is parallel to the view direction");
+        return VR_EINVAL;
+    }
+    if (cam->ortho != 0 && cam->ortho != 1) {
+        set_error("camera: ortho must be 0 or 1");
+        return VR_EINVAL;
+    }
+    if (cam->ortho) {
+        if (!(cam->ortho_w > 0.0) || !(cam->ortho_h > 0.0) || !std::isfinite(cam->ortho_w) ||
+            !std::isfinite(cam->ortho_h)) {
+            set_error("camera: orthographic window must be positive and finite");
+            return VR_EINVAL;
+        }
+    } else if (!(cam->fovy_deg > 0.0 && cam->fovy_deg < 180.0)) {
+        set_error("camera: fovy_deg must lie in (0, 180)");
+        return VR_EINVAL;
+    }
+    return VR_OK;
+}
+
+vr_status check_params(const vr_render_params* p) {
+    if (!p) {
+        set_error("render params are NULL");
+        return VR_EINVAL;
+    }
+    if (p->mode != VR_EA && p->mode != VR_MIP) {
+        set_error("mode must be VR_EA or VR_MIP");
+        return VR_EINVAL;
+    }
+    if (p->interp != VR_NEAREST && p->interp != VR_TRILINEAR) {
+        set_error("interp must be VR_NEAREST or VR_TRILINEAR");
+        return VR_EINVAL;
+    }
+    if (!(p->step >= 1e-3f && p->step <= 1e6f)) {
+        set_error("step must lie in [1e-3, 1e6] voxels");
+        return VR_EINVAL;
+    }
+    if (!(p->ert_alpha > 0.0f) || std::isnan(p->ert_alpha)) {
+        set_error("ert_alpha must be > 0 (values > 1 disable early termination)");
+        return VR_EINVAL;
+    }
+    if (p->width < 1 || p->height < 1 || p->width > 16384 || p->height > 16384) {
+        set_error("width and height must lie in [1, 16384]");
+        return VR_EINVAL;
+    }
+    if (p->use_skip != 0 && p->use_skip != 1) {
+        set_error("use_skip must be 0 or 1");
+        return VR_EINVAL;
+    }
+    return VR_OK;
+}
+
+vr_status check_tf(const float* rgbk, int32_t n, float v0, float v1) {
+    if (!rgbk) {
+        set_error("transfer function table is NULL");
+        return VR_EINVAL;
+    }
+    if (n < 2 || n > 4096) {
+        set_error("transfer function needs 2..4096 rows");
+        return VR_EINVAL;
+    }
+    if (!std::isfinite(v0) || !std::isfinite(v1) || !(v1 > v0)) {
+        set_error("transfer function domain needs finite v0 < v1");
+        return VR_EINVAL;
+    }
+    for (int i = 0; i < 4 * n; ++i) {
+        if (!std::isfinite(rgbk[i])) {
+            set_error("transfer function entries must be finite");
+            return VR_EINVAL;
+        }
+        if (i % 4 == 3 && rgbk[i] < 0.0f) {
+            set_error("extinction (4th channel) must be >= 0");
+            return VR_EINVAL;
+        }
+    }
+    return VR_OK;
+}
+
+static ff to_ff(double x) {
+    ff v;
+    v.hi = (float)x;
+    v.lo = std::isfinite(x) ? (float)(x - (double)v.hi) : 0.0f;
+    return v;
+}
+
+void camera_setup(const vr_camera& cam, int W, int H, DevCam& out) {
+    double f[3], r[3], u[3];
+    for (int a = 0; a < 3; ++a) f[a] = cam.target[a] - cam.eye[a];
+    double fl = std::sqrt(f[0] * f[0] + f[1] * f[1] + f[2] * f[2]);
+    for (int a = 0; a < 3; ++a) f[a] /= fl;
+    r[0] = f[1] * cam.up[2] - f[2] * cam.up[1];
+    r[1] = f[2] * cam.up[0] - f[0] * cam.up[2];
+    r[2] = f[0] * cam.up[1] - f[1] * cam.up[0];
+    double rl = std::sqrt(r[0] * r[0] + r[1] * r[1] + r[2] * r[2]);
+    for (int a = 0; a < 3; ++a) r[a] /= rl;
+    u[0] = r[1] * f[2] - r[2] * f[1];
+    u[1] = r[2] * f[0] - r[0] * f[2];
+    u[2] = r[0] * f[1] - r[1] * f[0];
+    std::memset(&out, 0, sizeof(out));
+    out.ortho = cam.ortho;
+    if (cam.ortho) {
+        const double w = cam.ortho_w, h = cam.ortho_h;
+        for (int a = 0; a < 3; ++a) {
+            out.o[a] = to_ff(cam.target[a] - 0.5 * w * r[a] + 0.5 * h * u[a]);
+            out.dx[a] = to_ff((w / W) * r[a]);
+            out.dy[a] = to_ff(-(h / H) * u[a]);
+            out.dir[a] = to_ff(f[a]);
+        }
+    } else {
+        const double h = std::tan(0.5 * cam.fovy_deg * (3.14159265358979323846 / 180.0));
+        const double asp = (double)W / (double)H;
+        for (int a = 0; a < 3; ++a) {
+            out.o[a] = to_ff(cam.eye[a]);
+            out.base[a] = to_ff(f[a] - h * asp * r[a] + h * u[a]);
+            out.dx[a] = to_ff((2.0 * h * asp / W) * r[a]);
+            out.dy[a] = to_ff(-(2.0 * h / H) * u[a]);
+        }
+    }
+}
+
+Cube* find_cube(Ctx* c, vr_cube id) {
+    auto it = c->cubes.find(id);
+    return it == c->cubes.end() ? nullptr : it->second.get();
+}
+
+Tf* find_tf(Ctx* c, vr_tf id) {
+    auto it = c->tfs.find(id);
+    return it == c->tfs.end() ? nullptr : it->second.get();
+}
+
+static vr_status ensure_event(hipEvent_t& e) {
+    if (e) return VR_OK;
+    return hip_check(hipEventCreateWithFlags(&e, hipEventDisableTiming), "hipEventCreate");
+}
+
+// skip mask for (mode, transfer function, clip) on this cube, classified on s if absent
+static vr_status get_mask(Ctx* c, Cube* cube, int mode, Tf* tf, float clip_s, hipStream_t s,
+                          MaskEntry** out) {
+    const int64_t ver = mode == VR_EA ? tf->version : -1;
+    uint32_t cb;
+    std::memcpy(&cb, &clip_s, 4);
+    for (auto& m : cube->masks) {
+        if (m.mode == mode && m.tf_version == ver && m.clip_bits == cb) {
+            m.stamp = ++c->mask_stamp;
+            *out = &m;
+            return VR_OK;
+        }
+    }
+    MaskEntry* e = nullptr;
+    if (cube->masks.size() < 8) {
+        cube->masks.emplace_back();
+        e = &cube->masks.back();
+        vr_status st = dev_alloc(c, e->buf, (uint64_t)cube->nslots * 8, true);
+        if (st != VR_OK) {
+            cube->masks.pop_back();
+            return st;
+        }
+        st = ensure_event(e->last_use);
+        if (st != VR_OK) return st;
+    } else {
+        e = &*std::min_element(cube->masks.begin(), cube->masks.end(),
+                               [](const MaskEntry& a, const MaskEntry& b) { return a.stamp < b.stamp; });
+        // the entry may still be read by queued work on another stream
+        vr_status st = hip_check(hipStreamWaitEvent(s, e->last_use, 0), "hipStreamWaitEvent");
+        if (st != VR_OK) return st;
+    }
+    float scale = 1.0f, bias = 0.0f;
+    int n = 2;
+    const int* kpos = nullptr;
+    if (mode == VR_EA) {
+        const double k = (double)(tf->n - 1) / ((double)tf->v1 - (double)tf->v0);
+        scale = (float)(cube->sigma * k);
+        bias = (float)(-(double)tf->v0 * k);
+        n = tf->n;
+        kpos = (const int*)tf->dev_kpos.ptr;
+    }
+    vr_status st = hip_check(vr_launch_classify((const float*)cube->cellmm.ptr, (uint64_t*)e->buf.ptr,
+                                                cube->nslots, mode, clip_s, scale, bias, n, kpos, s),
+                             "classify launch");
+    if (st != VR_OK) return st;
+    e->mode = mode;
+    e->tf_version = ver;
+    e->clip_bits = cb;
+    e->stamp = ++c->mask_stamp;
+    *out = e;
+    return VR_OK;
+}
+
+vr_status build_request(Ctx* c, Cube* cube, Tf* tf, float clip, const vr_camera& cam,
+                        const vr_render_params& p, void* out, hipStream_t s, DevReq& R,
+                        MaskEntry** mask_used) {
+    std::memset(&R, 0, sizeof(R));
+    if (mask_used) *mask_used = nullptr;
+    // sample count per ray must stay exactly representable
+    const double diag = std::sqrt((double)cube->nx * cube->nx + (double)cube->ny * cube->ny +
+                                  (double)cube->nz * cube->nz);
+    if (diag / p.step > 4.0e6) {
+        set_error("step too small for this cube (more than 4e6 samples per ray)");
+        return VR_EINVAL;
+    }
+    R.cube.pool = (const uint8_t*)cube->pool.ptr;
+    R.cube.slot_of_brick = (const uint32_t*)cube->slots.ptr;
+    R.cube.stride = cube->stride;
+    R.cube.nx = (int)cube->nx;
+    R.cube.ny = (int)cube->ny;
+    R.cube.nz = (int)cube->nz;
+    R.cube.bx = cube->Bx;
+    R.cube.by = cube->By;
+    R.cube.bz = cube->Bz;
+    R.cube.dtype = cube->storage;
+    const float clip_s = std::isfinite(clip) ? (float)((double)clip / cube->sigma) : clip;
+    R.tf.clip = clip_s;
+    if (p.mode == VR_EA) {
+        const double k = (double)(tf->n - 1) / ((double)tf->v1 - (double)tf->v0);
+        R.tf.rows = (const float*)tf->dev_rows.ptr;
+        R.tf.n = tf->n;
+        R.tf.scale = (float)(cube->sigma * k);
+        R.tf.bias = (float)(-(double)tf->v0 * k);
+    } else {
+        R.tf.n = 2;
+    }
+    camera_setup(cam, p.width, p.height, R.cam);
+    R.out = (float*)out;
+    R.W = p.width;
+    R.H = p.height;
+    R.tiles_x = (p.width + VR_TILE - 1) / VR_TILE;
+    R.tiles_y = (p.height + VR_TILE - 1) / VR_TILE;
+    R.mode = p.mode;
+    R.interp = p.interp;
+    R.use_skip = p.use_skip;
+    R.step = ff{p.step, 0.0f};
+    R.ert_T = p.ert_alpha > 1.0f ? -1.0f : (float)(1.0 - (double)p.ert_alpha);
+    R.out_scale = (float)cube->sigma;
+    if (p.use_skip) {
+        MaskEntry* me = nullptr;
+        vr_status st = get_mask(c, cube, p.mode, tf, clip_s, s, &me);
+        if (st != VR_OK) return st;
+        R.cube.mask = (const uint64_t*)me->buf.ptr;
+        if (mask_used) *mask_used = me;
+    }
+    return VR_OK;
+}
+
+vr_status mark_use(Ctx* c, Cube* cube, Tf* tf, MaskEntry* mask, hipStream_t s) {
+    (void)c;
+    vr_status st = ensure_event(cube->last_use);
+    if (st != VR_OK) return st;
+    st = hip_check(hipEventRecord(cube->last_use, s), "hipEventRecord");
+    if (st != VR_OK) return st;
+    if (mask) {
+        st = hip_check(hipEventRecord(mask->last_use, s), "hipEventRecord");
+        if (st != VR_OK) return st;
+    }
+    if (tf) {
+        st = ensure_event(tf->last_use);
+        if (st != VR_OK) return st;
+        st = hip_check(hipEventRecord(tf->last_use, s), "hipEventRecord");
+        if (st != VR_OK) return st;
+    }
+    return VR_OK;
+}
+
+static vr_status ensure_counters(Ctx* c, int count) {
+    if (c->counters_cap >= count) return VR_OK;
+    if (c->counters.ptr) {
+        vr_status st = hip_check(hipDeviceSynchronize(), "hipDeviceSynchronize");
+        if (st != VR_OK) return st;
+        dev_free(c, c->counters, false);
+    }
+    int cap = std::max(count, 64);
+    vr_status st = dev_alloc(c, c->counters, (uint64_t)cap * sizeof(DevCounters), false);
+    if (st != VR_OK) return st;
+    c->counters_cap = cap;
+    return VR_OK;
+}
+
+static void fill_stats(const DevCounters& d, float ms, vr_stats* st) {
+    st->samples_nominal = d.samples_nominal;
+    st->samples_exec = d.samples_exec;
+    st->rays_hit = d.rays_hit;
+    st->rays_ert = d.rays_ert;
+    st->cells_skipped = d.cells_skipped;
+    st->kernel_ms = ms;
+    st->reserved = 0.0f;
+}
+
+vr_status check_request(Ctx* c, const vr_request* r) {
+    if (!r) {
+        set_error("request is NULL");
+        return VR_EINVAL;
+    }
+    vr_status st = check_params(&r->params);
+    if (st != VR_OK) return st;
+    st = check_camera(&r->camera);
+    if (st != VR_OK) return st;
+    if (!r->out_dev) {
+        set_error("request output pointer is NULL");
+        return VR_EINVAL;
+    }
+    if (std::isnan(r->clip)) {
+        set_error("clip must not be NaN");
+        return VR_EINVAL;
+    }
+    if (!find_cube(c, r->cube)) {
+        set_error("unknown cube handle " + std::to_string(r->cube));
+        return VR_ENOTFOUND;
+    }
+    if (r->params.mode == VR_EA) {
+        const vr_tf t = r->tf ? r->tf : c->current_tf;
+        if (!t) {
+            set_error("no transfer function set");
+            return VR_ESTATE;
+        }
+        if (!find_tf(c, t)) {
+            set_error("unknown transfer function handle " + std::to_string(t));
+            return VR_ENOTFOUND;
+        }
+    }
+    return VR_OK;
+}
+
+void free_batch_bufs(Ctx* c, BatchBufs& bb) {
+    dev_free(c, bb.reqs, false);
+    dev_free(c, bb.items, false);
+    dev_free(c, bb.head, false);
+    if (bb.pin_reqs) (void)hipHostFree(bb.pin_reqs);
+    if (bb.pin_items) (void)hipHostFree(bb.pin_items);
+    bb.pin_reqs = nullptr;
+    bb.pin_items = nullptr;
+    bb.reqs_cap = bb.items_cap = 0;
+    if (bb.done) (void)hipEventDestroy(bb.done);
+    bb.done = nullptr;
+}
+
+static vr_status grow_batch(Ctx* c, BatchBufs& bb, int nreq, int nitems) {
+    vr_status st = ensure_event(bb.done);
+    if (st != VR_OK) return st;
+    // staging may still feed a queued copy
+    st = hip_check(hipEventSynchronize(bb.done), "hipEventSynchronize");
+    if (st != VR_OK) return st;
+    if (!bb.head.ptr) {
+        st = dev_alloc(c, bb.head, 256, false);
+        if (st != VR_OK) return st;
+    }
+    if (bb.reqs_cap < nreq) {
+        int cap = std::max(nreq, 64);
+        dev_free(c, bb.reqs, false);
+        if (bb.pin_reqs) (void)hipHostFree(bb.pin_reqs);
+        bb.pin_reqs = nullptr;
+        bb.reqs_cap = 0;
+        st = dev_alloc(c, bb.reqs, (uint64_t)cap * sizeof(DevReq), false);
+        if (st != VR_OK) return st;
+        st = hip_check(hipHostMalloc((void**)&bb.pin_reqs, (size_t)cap * sizeof(DevReq), 0),
+                       "hipHostMalloc");
+        if (st != VR_OK) return st;
+        bb.reqs_cap = cap;
+    }
+    if (bb.items_cap < nitems) {
+        int cap = std::max(nitems, 4096);
+        dev_free(c, bb.items, false);
+        if (bb.pin_items) (void)hipHostFree(bb.pin_items);
+        bb.pin_items = nullptr;
+        bb.items_cap = 0;
+        st = dev_alloc(c, bb.items, (uint64_t)cap * sizeof(DevItem), false);
+        if (st != VR_OK) return st;
+        st = hip_check(hipHostMalloc((void**)&bb.pin_items, (size_t)cap * sizeof(DevItem), 0),
+                       "hipHostMalloc");
+        if (st != VR_OK) return st;
+        bb.items_cap = cap;
+    }
+    return VR_OK;
+}
+
+vr_status launch_requests(Ctx* c, BatchBufs& bb, const vr_request* reqs, int count,
+                          const int32_t* tiles, hipStream_t s, DevCounters* dev_counters) {
+    int nitems = 0;
+    for (int r = 0; r < count; ++r) {
+        const auto& p = reqs[r].params;
+        const int nt = ((p.width + VR_TILE - 1) / VR_TILE) * ((p.height + VR_TILE - 1) / VR_TILE);
+        nitems += tiles ? (tiles[2 * r + 1] - tiles[2 * r]) : nt;
+    }
+    vr_status st = grow_batch(c, bb, count, std::max(nitems, 1));
+    if (st != VR_OK) return st;
+    int max_tf_n = 0, k = 0;
+    std::vector<MaskEntry*> used((size_t)count, nullptr);
+    for (int r = 0; r < count; ++r) {
+        const vr_request& q = reqs[r];
+        Cube* cube = find_cube(c, q.cube);
+        Tf* tf = q.params.mode == VR_EA ? find_tf(c, q.tf ? q.tf : c->current_tf) : nullptr;
+        st = build_request(c, cube, tf, q.clip, q.camera, q.params, q.out_dev, s, bb.pin_reqs[r],
+                           &used[(size_t)r]);
+        if (st != VR_OK) return st;
+        if (tf) max_tf_n = std::max(max_tf_n, tf->n);
+        const DevReq& R = bb.pin_reqs[r];
+        const int t0 = tiles ? tiles[2 * r] : 0;
+        const int t1 = tiles ? tiles[2 * r + 1] : R.tiles_x * R.tiles_y;
+        for (int t = t0; t < t1; ++t) bb.pin_items[k++] = DevItem{r, t};
+    }
+    st = hip_check(hipMemcpyAsync(bb.reqs.ptr, bb.pin_reqs, (size_t)count * sizeof(DevReq),
+                                  hipMemcpyHostToDevice, s),
+                   "hipMemcpyAsync");
+    if (st != VR_OK) return st;
+    if (nitems > 0) {
+        st = hip_check(hipMemcpyAsync(bb.items.ptr, bb.pin_items, (size_t)nitems * sizeof(DevItem),
+                                      hipMemcpyHostToDevice, s),
+                       "hipMemcpyAsync");
+        if (st != VR_OK) return st;
+    }
+    const int grid = std::max(1, std::min(nitems, c->num_cu * 4));
+    if (nitems > 0) {
+        st = hip_check(vr_launch_batch((const DevReq*)bb.reqs.ptr, (const DevItem*)bb.items.ptr,
+                                       nitems, (unsigned*)bb.head.ptr, dev_counters, max_tf_n, grid,
+                                       s),
+                       "batch launch");
+        if (st != VR_OK) return st;
+    }
+    st = hip_check(hipEventRecord(bb.done, s), "hipEventRecord");
+    if (st != VR_OK) return st;
+    for (int r = 0; r < count; ++r) {
+        const vr_request& q = reqs[r];
+        Tf* tf = q.params.mode == VR_EA ? find_tf(c, q.tf ? q.tf : c->current_tf) : nullptr;
+        st = mark_use(c, find_cube(c, q.cube), tf, used[(size_t)r], s);
+        if (st != VR_OK) return st;
+    }
+    return VR_OK;
+}
+
+static vr_status make_tf(Ctx* c, const float* rgbk, int32_t n, float v0, float v1, Tf** out) {
+    std::unique_ptr<Tf> t(new Tf());
+    t->id = c->next_tf++;
+    t->version = c->next_tf_version++;
+    t->n = n;
+    t->v0 = v0;
+    t->v1 = v1;
+    t->rows.assign(rgbk, rgbk + 4 * n);
+    if (!c->host_only()) {
+        std::vector<float> dev(8 * (size_t)n, 0.0f);
+        for (int i = 0; i < n; ++i)
+            for (int ch = 0; ch < 4; ++ch) {
+                dev[8 * i + ch] = rgbk[4 * i + ch];
+                dev[8 * i + 4 + ch] = i + 1 < n ? rgbk[4 * (i + 1) + ch] - rgbk[4 * i + ch] : 0.0f;
+            }
+        std::vector<int> kpos((size_t)n + 2, 0);
+        for (int i = 0; i < n; ++i) kpos[i + 1] = kpos[i] + (rgbk[4 * i + 3] > 0.0f ? 1 : 0);
+        kpos[n + 1] = kpos[n];
+        vr_status st = dev_alloc(c, t->dev_rows, dev.size() * 4, false);
+        if (st != VR_OK) return st;
+        st = dev_alloc(c, t->dev_kpos, kpos.size() * 4, false);
+        if (st != VR_OK) {
+            dev_free(c, t->dev_rows, false);
+            return st;
+        }
+        st = hip_check(hipMemcpy(t->dev_rows.ptr, dev.data(), dev.size() * 4, hipMemcpyHostToDevice),
+                       "hipMemcpy");
+        if (st == VR_OK)
+            st = hip_check(hipMemcpy(t->dev_kpos.ptr, kpos.data(), kpos.size() * 4,
+                                     hipMemcpyHostToDevice),
+                           "hipMemcpy");
+        if (st != VR_OK) {
+            dev_free(c, t->dev_rows, false);
+            dev_free(c, t->dev_kpos, false);
+            return st;
+        }
+    }
+    *out = t.get();
+    c->tfs[t->id] = std::move(t);
+    return VR_OK;
+}
+
+static vr_status release_tf(Ctx* c, Tf* t) {
+    if (t->last_use) {
+        vr_status st = hip_check(hipEventSynchronize(t->last_use), "hipEventSynchronize");
+        if (st != VR_OK) return st;
+        (void)hipEventDestroy(t->last_use);
+    }
+    dev_free(c, t->dev_rows, false);
+    dev_free(c, t->dev_kpos, false);
+    c->tfs.erase(t->id);
+    return VR_OK;
+}
+
+static vr_status release_cube(Ctx* c, Cube* cube) {
+    if (cube->last_use) {
+        vr_status st = hip_check(hipEventSynchronize(cube->last_use), "hipEventSynchronize");
+        if (st != VR_OK) return st;
+        (void)hipEventDestroy(cube->last_use);
+    }
+    for (auto& m : cube->masks) {
+        dev_free(c, m.buf, true);
+        if (m.last_use) (void)hipEventDestroy(m.last_use);
+    }
+    dev_free(c, cube->pool, true);
+    dev_free(c, cube->slots, true);
+    dev_free(c, cube->cellmm, true);
+    c->cubes.erase(cube->id);
+    return VR_OK;
+}
+
+static uint64_t morton3(uint32_t x, uint32_t y, uint32_t z) {
+    auto spread = [](uint64_t v) {
+        v &= 0x1FFFFF;
+        v = (v | v << 32) & 0x1F00000000FFFFull;
+        v = (v | v << 16) & 0x1F0000FF0000FFull;
+        v = (v | v << 8) & 0x100F00F00F00F00Full;
+        v = (v | v << 4) & 0x10C30C30C30C30C3ull;
+        v = (v | v << 2) & 0x1249249249249249ull;
+        return v;
+    };
+    return spread(x) | (spread(y) << 1) | (spread(z) << 2);
+}
+
+}  // namespace vrh
+
+using namespace vrh;
+
+// no C++ exception crosses the C interface
+#define VR_GUARD(...)                                           \
+    try {                                                       \
+        __VA_ARGS__                                             \
+    } catch (const std::bad_alloc&) {                           \
+        set_error("host allocation failed");                    \
+        return VR_ENOMEM;                                       \
+    } catch (const std::exception& ex) {                        \
+        set_error(std::string("internal error: ") + ex.what()); \
+        return VR_EINVAL;                                       \
+    } catch (...) {                                             \
+        set_error("internal error");                            \
+        return VR_EINVAL;                                       \
+    }
+
+extern "C" {
+
+const char* vr_last_error(void) { return g_err.c_str(); }
+
+const char* vr_version(void) { return "vr-mi355x 0.1 (gfx950)"; }
+
+vr_status vr_create(int32_t device, uint64_t hbm_budget_bytes, const vr_allocator* alloc,
+                    vr_ctx* out) {
+    if (!out) {
+        set_error("out is NULL");
+        return VR_EINVAL;
+    }
+    *out = nullptr;
+    if (device < -1) {
+        set_error("device must be >= 0, or -1 for a host-only context");
+        return VR_EINVAL;
+    }
+    if (alloc && (!alloc->alloc || !alloc->free)) {
+        set_error("allocator needs both alloc and free");
+        return VR_EINVAL;
+    }
+    VR_GUARD({
+        std::unique_ptr<Ctx> c(new Ctx());
+        c->device = device;
+        c->budget = hbm_budget_bytes;
+        if (alloc) {
+            c->has_alloc = true;
+            c->alloc = *alloc;
+        }
+        if (device >= 0) {
+            int n = 0;
+            vr_status st = hip_check(hipGetDeviceCount(&n), "hipGetDeviceCount");
+            if (st != VR_OK) return st;
+            if (device >= n) {
+                set_error("device index out of range");
+                return VR_EINVAL;
+            }
+            st = hip_check(hipSetDevice(device), "hipSetDevice");
+            if (st != VR_OK) return st;
+            hipDeviceProp_t prop;
+            st = hip_check(hipGetDeviceProperties(&prop, device), "hipGetDeviceProperties");
+            if (st != VR_OK) return st;
+            c->num_cu = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 256;
+        }
+        *out = (vr_ctx)c.release();
+        return VR_OK;
+    });
+}
+
+vr_status vr_destroy(vr_ctx ctx) {
+    if (!ctx) {
+        set_error("ctx is NULL");
+        return VR_EINVAL;
+    }
+    Ctx* c = (Ctx*)ctx;
+    VR_GUARD({
+        if (c->server) server_stop(c);
+        std::lock_guard<std::recursive_mutex> lk(c->mu);
+        if (!c->host_only()) {
+            (void)hipSetDevice(c->device);
+            (void)hipDeviceSynchronize();
+            std::vector<Cube*> cs;
+            for (auto& kv : c->cubes) cs.push_back(kv.second.get());
+            for (Cube* cu : cs) release_cube(c, cu);
+            std::vector<Tf*> ts;
+            for (auto& kv : c->tfs) ts.push_back(kv.second.get());
+            for (Tf* t : ts) release_tf(c, t);
+            dev_free(c, c->counters, false);
+            free_batch_bufs(c, c->batch);
+        }
+    });
+    delete c;
+    return VR_OK;
+}
+
+vr_status vr_cube_upload(vr_ctx ctx, const void* src, int32_t src_dtype, int32_t src_on_device,
+                         int64_t nx, int64_t ny, int64_t nz, int32_t storage, double sigma_scale,
+                         void* hip_stream, vr_cube* out) {
+    if (!ctx || !out || !src) {
+        set_error("ctx, src and out must be non-NULL");
+        return VR_EINVAL;
+    }
+    *out = 0;
+    if (nx < 2 || ny < 2 || nz < 2 || nx > 65536 || ny > 65536 || nz > 65536) {
+        set_error("cube dimensions must lie in [2, 65536]");
+        return VR_EINVAL;
+    }
+    if (storage != VR_F32 && storage != VR_F16 && storage != VR_BF16) {
+        set_error("storage must be VR_F32, VR_F16 or VR_BF16");
+        return VR_EINVAL;
+    }
+    if (src_dtype != VR_F32 && src_dtype != VR_F16 && src_dtype != VR_BF16) {
+        set_error("src_dtype must be VR_F32, VR_F16 or VR_BF16");
+        return VR_EINVAL;
+    }
+    if (src_dtype != VR_F32 && src_dtype != storage) {
+        set_error("16-bit sources are stored as-is: storage must equal src_dtype");
+        return VR_EUNSUPPORTED;
+    }
+    if (src_on_device != 0 && src_on_device != 1) {
+        set_error("src_on_device must be 0 or 1");
+        return VR_EINVAL;
+    }
+    if (!(sigma_scale > 0.0) || !std::isfinite(sigma_scale)) {
+        set_error("sigma_scale must be positive and finite");
+        return VR_EINVAL;
+    }
+    Ctx* c = (Ctx*)ctx;
+    VR_GUARD({
+        std::lock_guard<std::recursive_mutex> lk(c->mu);
+        if (c->host_only()) {
+            set_error("host-only context cannot hold cubes");
+            return VR_EDEVICE;
+        }
+        vr_status st = hip_check(hipSetDevice(c->device), "hipSetDevice");
+        if (st != VR_OK) return st;
+        hipStream_t s = (hipStream_t)hip_stream;
+        std::unique_ptr<Cube> cube(new Cube());
+        cube->nx = nx;
+        cube->ny = ny;
+        cube->nz = nz;
+        cube->storage = storage;
+        cube->sigma = sigma_scale;
+        cube->Bx = (int)((nx + VR_BRICK - 1) / VR_BRICK);
+        cube->By = (int)((ny + VR_BRICK - 1) / VR_BRICK);
+        cube->Bz = (int)((nz + VR_BRICK - 1) / VR_BRICK);
+        const int64_t ns = (int64_t)cube->Bx * cube->By * cube->Bz;
+        if (ns > (int64_t)1 << 30) {
+            set_error("cube too large");
+            return VR_EINVAL;
+        }
+        cube->nslots = (int)ns;
+        const uint64_t elem = storage == VR_F32 ? 4 : 2;
+        cube->stride = (VR_BRICK_APRON * VR_BRICK_APRON * VR_BRICK_APRON * elem + 255) & ~uint64_t(255);
+        auto cleanup = [&]() {
+            dev_free(c, cube->pool, true);
+            dev_free(c, cube->slots, true);
+            dev_free(c, cube->cellmm, true);
+        };
+        st = dev_alloc(c, cube->pool, (uint64_t)ns * cube->stride, true);
+        if (st == VR_OK) st = dev_alloc(c, cube->slots, (uint64_t)ns * 4, true);
+        if (st == VR_OK)
+            st = dev_alloc(c, cube->cellmm, (uint64_t)ns * 2 * VR_CELLS_PER_BRICK * 4, true);
+        if (st != VR_OK) {
+            cleanup();
+            return st;
+        }
+        // Morton-ordered slots
+        std::vector<uint32_t> order((size_t)ns);
+        std::iota(order.begin(), order.end(), 0u);
+        std::vector<uint64_t> code((size_t)ns);
+        for (int64_t b = 0; b < ns; ++b) {
+            const uint32_t bx = (uint32_t)(b % cube->Bx), by = (uint32_t)((b / cube->Bx) % cube->By),
+                           bz = (uint32_t)(b / ((int64_t)cube->Bx * cube->By));
+            code[(size_t)b] = morton3(bx, by, bz);
+        }
+        std::sort(order.begin(), order.end(),
+                  [&](uint32_t a, uint32_t b) { return code[a] < code[b]; });
+        std::vector<uint32_t> slot_of((size_t)ns);
+        for (int64_t r = 0; r < ns; ++r) slot_of[order[(size_t)r]] = (uint32_t)r;
+        st = hip_check(hipMemcpy(cube->slots.ptr, slot_of.data(), (size_t)ns * 4,
+                                 hipMemcpyHostToDevice),
+                       "hipMemcpy");
+        if (st != VR_OK) {
+            cleanup();
+            return st;
+        }
+        const int src_kind = src_dtype == VR_F32 ? 0 : src_dtype;
+        const uint64_t selem = src_dtype == VR_F32 ? 4 : 2;
+        const uint64_t plane = (uint64_t)nx * ny * selem;
+        DevBuf stage;
+        if (!src_on_device) {
+            st = dev_alloc(c, stage, plane * (uint64_t)std::min<int64_t>(nz, VR_BRICK_APRON), false);
+            if (st != VR_OK) {
+                cleanup();
+                return st;
+            }
+        }
+        for (int bz = 0; bz < cube->Bz && st == VR_OK; ++bz) {
+            const int64_t z0 = (int64_t)bz * VR_BRICK;
+            const int64_t z1 = std::min<int64_t>(z0 + VR_BRICK_APRON, nz);
+            const void* slab = src;
+            int64_t z_first = 0;
+            if (!src_on_device) {
+                st = hip_check(hipMemcpyAsync(stage.ptr, (const uint8_t*)src + (uint64_t)z0 * plane,
+                                              (size_t)((z1 - z0) * plane), hipMemcpyHostToDevice, s),
+                               "hipMemcpyAsync");
+                if (st != VR_OK) break;
+                slab = stage.ptr;
+                z_first = z0;
+            }
+            st = hip_check(vr_launch_brick_build(src_kind, storage, slab, nx, ny, nz, z_first, bz,
+                                                 cube->Bx, cube->By, (const uint32_t*)cube->slots.ptr,
+                                                 (uint8_t*)cube->pool.ptr, cube->stride,
+                                                 (float*)cube->cellmm.ptr, (float)sigma_scale, s),
+                           "brick build launch");
+        }
+        vr_status st2 = hip_check(hipStreamSynchronize(s), "hipStreamSynchronize");
+        if (stage.ptr) dev_free(c, stage, false);
+        if (st == VR_OK) st = st2;
+        if (st != VR_OK) {
+            cleanup();
+            return st;
+        }
+        cube->id = c->next_cube++;
+        *out = cube->id;
+        c->cubes[cube->id] = std::move(cube);
+        return VR_OK;
+    });
+}
+
+vr_status vr_cube_release(vr_ctx ctx, vr_cube cube) {
+    if (!ctx) {
+        set_error("ctx is NULL");
+        return VR_EINVAL;
+    }
+    Ctx* c = (Ctx*)ctx;
+    VR_GUARD({
+        std::lock_guard<std::recursive_mutex> lk(c->mu);
+        Cube* cu = find_cube(c, cube);
+        if (!cu) {
+            set_error("unknown cube handle " + std::to_string(cube));
+            return VR_ENOTFOUND;
+        }
+        if (cu->refs > 0) {
+            set_error("cube is referenced by queued requests");
+            return VR_EBUSY;
+        }
+        (void)hipSetDevice(c->device);
+        return release_cube(c, cu);
+    });
+}
+
+vr_status vr_cube_get_info(vr_ctx ctx, vr_cube cube, vr_cube_info* out) {
+    if (!ctx || !out) {
+        set_error("ctx and out must be non-NULL");
+        return VR_EINVAL;
+    }
+    Ctx* c = (Ctx*)ctx;
+    VR_GUARD({
+        std::lock_guard<std::recursive_mutex> lk(c->mu);
+        Cube* cu = find_cube(c, cube);
+        if (!cu) {
+            set_error("unknown cube handle " + std::to_string(cube));
+            return VR_ENOTFOUND;
+        }
+        std::memset(out, 0, sizeof(*out));
+        out->nx = cu->nx;
+        out->ny = cu->ny;
+        out->nz = cu->nz;
+        out->storage = cu->storage;
+        out->brick = VR_BRICK;
+        out->bricks_x = cu->Bx;
+        out->bricks_y = cu->By;
+        out->bricks_z = cu->Bz;
+        out->cell = VR_CELL;
+        out->sigma_scale = cu->sigma;
+        out->pool_bytes = cu->pool.bytes;
+        out->brick_stride = cu->stride;
+        out->aux_bytes = cu->bytes() - cu->pool.bytes;
+        out->pool = cu->pool.ptr;
+        out->slot_of_brick = (const uint32_t*)cu->slots.ptr;
+        out->cell_minmax = (const float*)cu->cellmm.ptr;
+        (void)hipSetDevice(c->device);
+        std::vector<float> mm((size_t)cu->nslots * 2 * VR_CELLS_PER_BRICK);
+        vr_status st = hip_check(hipMemcpy(mm.data(), cu->cellmm.ptr, mm.size() * 4,
+                                           hipMemcpyDeviceToHost),
+                                 "hipMemcpy");
+        if (st != VR_OK) return st;
+        float lo = __builtin_huge_valf(), hi = -__builtin_huge_valf();
+        for (size_t i = 0; i < mm.size(); i += 2) {
+            lo = std::min(lo, mm[i]);
+            hi = std::max(hi, mm[i + 1]);
+        }
+        out->vmin = (float)(lo * cu->sigma);
+        out->vmax = (float)(hi * cu->sigma);
+        return VR_OK;
+    });
+}
+
+vr_status vr_set_transfer_function(vr_ctx ctx, const float* rgbk, int32_t n, float v0, float v1) {
+    if (!ctx) {
+        set_error("ctx is NULL");
+        return VR_EINVAL;
+    }
+    vr_status st = check_tf(rgbk, n, v0, v1);
+    if (st != VR_OK) return st;
+    Ctx* c = (Ctx*)ctx;
+    VR_GUARD({
+        std::lock_guard<std::recursive_mutex> lk(c->mu);
+        if (!c->host_only()) (void)hipSetDevice(c->device);
+        Tf* t = nullptr;
+        st = make_tf(c, rgbk, n, v0, v1, &t);
+        if (st != VR_OK) return st;
+        t->internal = true;
+        // the previous internal table goes once no queued request holds it
+        // (release waits for queued kernels that read it)
+        if (c->current_tf) {
+            Tf* old = find_tf(c, c->current_tf);
+            if (old && old->internal && old->refs == 0) release_tf(c, old);
+        }
+        c->current_tf = t->id;
+        return VR_OK;
+    });
+}
+
+vr_status vr_set_noise_clip(vr_ctx ctx, float k, float sigma) {
+    if (!ctx) {
+        set_error("ctx is NULL");
+        return VR_EINVAL;
+    }
+    if (!(sigma > 0.0f) || !std::isfinite(sigma)) {
+        set_error("sigma must be positive and finite");
+        return VR_EINVAL;
+    }
+    if (std::isnan(k) || k == __builtin_huge_valf()) {
+        set_error("k must be finite or -inf");
+        return VR_EINVAL;
+    }
+    Ctx* c = (Ctx*)ctx;
+    std::lock_guard<std::recursive_mutex> lk(c->mu);
+    c->clip = std::isfinite(k) ? (float)((double)k * (double)sigma) : k;
+    return VR_OK;
+}
+
+vr_status vr_set_camera(vr_ctx ctx, const vr_camera* cam) {
+    if (!ctx) {
+        set_error("ctx is NULL");
+        return VR_EINVAL;
+    }
+    vr_status st = check_camera(cam);
+    if (st != VR_OK) return st;
+    Ctx* c = (Ctx*)ctx;
+    std::lock_guard<std::recursive_mutex> lk(c->mu);
+    c->camera = *cam;
+    c->has_camera = true;
+    return VR_OK;
+}
+
+vr_status vr_render(vr_ctx ctx, vr_cube cube, const vr_render_params* params, void* out_dev,
+                    void* hip_stream, vr_stats* stats) {
+    if (!ctx) {
+        set_error("ctx is NULL");
+        return VR_EINVAL;
+    }
+    vr_status st = check_params(params);
+    if (st != VR_OK) return st;
+    if (!out_dev) {
+        set_error("out_dev is NULL");
+        return VR_EINVAL;
+    }
+    Ctx* c = (Ctx*)ctx;
+    VR_GUARD({
+        std::lock_guard<std::recursive_mutex> lk(c->mu);
+        if (!c->has_camera) {
+            set_error("camera not set");
+            return VR_ESTATE;
+        }
+        Tf* tf = nullptr;
+        if (params->mode == VR_EA) {
+            if (!c->current_tf) {
+                set_error("transfer function not set");
+                return VR_ESTATE;
+            }
+            tf = find_tf(c, c->current_tf);
+        }
+        Cube* cu = find_cube(c, cube);
+        if (!cu) {
+            set_error("unknown cube handle " + std::to_string(cube));
+            return VR_ENOTFOUND;
+        }
+        if (c->host_only()) {
+            set_error("host-only context cannot render");
+            return VR_EDEVICE;
+        }
+        st = hip_check(hipSetDevice(c->device), "hipSetDevice");
+        if (st != VR_OK) return st;
+        hipStream_t s = (hipStream_t)hip_stream;
+        DevReq R;
+        MaskEntry* me = nullptr;
+        st = build_request(c, cu, tf, c->clip, c->camera, *params, out_dev, s, R, &me);
+        if (st != VR_OK) return st;
+        DevCounters* dc = nullptr;
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        if (stats) {
+            st = ensure_counters(c, 1);
+            if (st != VR_OK) return st;
+            dc = (DevCounters*)c->counters.ptr;
+            st = hip_check(hipMemsetAsync(dc, 0, sizeof(DevCounters), s), "hipMemsetAsync");
+            if (st != VR_OK) return st;
+            st = hip_check(hipEventCreate(&e0), "hipEventCreate");
+            if (st == VR_OK) st = hip_check(hipEventCreate(&e1), "hipEventCreate");
+            if (st == VR_OK) st = hip_check(hipEventRecord(e0, s), "hipEventRecord");
+            if (st != VR_OK) return st;
+        }
+        st = hip_check(vr_launch_render(R, dc, s), "render launch");
+        if (st != VR_OK) return st;
+        st = mark_use(c, cu, tf, me, s);
+        if (st != VR_OK) return st;
+        if (stats) {
+            st = hip_check(hipEventRecord(e1, s), "hipEventRecord");
+            if (st == VR_OK) st = hip_check(hipEventSynchronize(e1), "render");
+            float ms = 0.0f;
+            if (st == VR_OK) st = hip_check(hipEventElapsedTime(&ms, e0, e1), "hipEventElapsedTime");
+            DevCounters h;
+            if (st == VR_OK)
+                st = hip_check(hipMemcpy(&h, dc, sizeof(h), hipMemcpyDeviceToHost), "hipMemcpy");
+            (void)hipEventDestroy(e0);
+            (void)hipEventDestroy(e1);
+            if (st != VR_OK) return st;
+            fill_stats(h, ms, stats);
+        }
+        return VR_OK;
+    });
+}
+
+vr_status vr_tf_create(vr_ctx ctx, const float* rgbk, int32_t n, float v0, float v1, vr_tf* out) {
+    if (!ctx || !out) {
+        set_error("ctx and out must be non-NULL");
+        return VR_EINVAL;
+    }
+    *out = 0;
+    vr_status st = check_tf(rgbk, n, v0, v1);
+    if (st != VR_OK) return st;
+    Ctx* c = (Ctx*)ctx;
+    VR_GUARD({
+        std::lock_guard<std::recursive_mutex> lk(c->mu);
+        if (!c->host_only()) (void)hipSetDevice(c->device);
+        Tf* t = nullptr;
+        st = make_tf(c, rgbk, n, v0, v1, &t);
+        if (st != VR_OK) return st;
+        *out = t->id;
+        return VR_OK;
+    });
+}
+
+vr_status vr_tf_release(vr_ctx ctx, vr_tf tf) {
+    if (!ctx) {
+        set_error("ctx is NULL");
+        return VR_EINVAL;
+    }
+    Ctx* c = (Ctx*)ctx;
+    VR_GUARD({
+        std::lock_guard<std::recursive_mutex> lk(c->mu);
+        Tf* t = find_tf(c, tf);
+        if (!t) {
+            set_error("unknown transfer function handle " + std::to_string(tf));
+            return VR_ENOTFOUND;
+        }
+        if (tf == c->current_tf) {
+            set_error("the context's current transfer function cannot be released");
+            return VR_EBUSY;
+        }
+        if (!c->host_only()) (void)hipSetDevice(c->device);
+        return release_tf(c, t);
+    });
+}
+
+vr_status vr_render_batch(vr_ctx ctx, const vr_request* reqs, int32_t count, void* hip_stream,
+                          vr_stats* stats) {
+    if (!ctx || (!reqs && count > 0)) {
+        set_error("ctx and reqs must be non-NULL");
+        return VR_EINVAL;
+    }
+    if (count < 0 || count > 4096) {
+        set_error("count must lie in [0, 4096]");
+        return VR_EINVAL;
+    }
+    Ctx* c = (Ctx*)ctx;
+    VR_GUARD({
+        std::lock_guard<std::recursive_mutex> lk(c->mu);
+        for (int r = 0; r < count; ++r) {
+            vr_status st = check_request(c, &reqs[r]);
+            if (st != VR_OK) {
+                set_error("request " + std::to_string(r) + ": " + g_err);
+                return st;
+            }
+        }
+        if (count == 0) return VR_OK;
+        if (c->host_only()) {
+            set_error("host-only context cannot render");
+            return VR_EDEVICE;
+        }
+        vr_status st = hip_check(hipSetDevice(c->device), "hipSetDevice");
+        if (st != VR_OK) return st;
+        hipStream_t s = (hipStream_t)hip_stream;
+        DevCounters* dc = nullptr;
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        if (stats) {
+            st = ensure_counters(c, count);
+            if (st != VR_OK) return st;
+            dc = (DevCounters*)c->counters.ptr;
+            st = hip_check(hipMemsetAsync(dc, 0, sizeof(DevCounters) * count, s), "hipMemsetAsync");
+            if (st == VR_OK) st = hip_check(hipEventCreate(&e0), "hipEventCreate");
+            if (st == VR_OK) st = hip_check(hipEventCreate(&e1), "hipEventCreate");
+            if (st == VR_OK) st = hip_check(hipEventRecord(e0, s), "hipEventRecord");
+            if (st != VR_OK) return st;
+        }
+        st = launch_requests(c, c->batch, reqs, count, nullptr, s, dc);
+        if (st != VR_OK) return st;
+        if (stats) {
+            st = hip_check(hipEventRecord(e1, s), "hipEventRecord");
+            if (st == VR_OK) st = hip_check(hipEventSynchronize(e1), "batch render");
+            float ms = 0.0f;
+            if (st == VR_OK) st = hip_check(hipEventElapsedTime(&ms, e0, e1), "hipEventElapsedTime");
+            std::vector<DevCounters> h((size_t)count);
+            if (st == VR_OK)
+                st = hip_check(hipMemcpy(h.data(), dc, sizeof(DevCounters) * count,
+                                         hipMemcpyDeviceToHost),
+                               "hipMemcpy");
+            (void)hipEventDestroy(e0);
+            (void)hipEventDestroy(e1);
+            if (st != VR_OK) return st;
+            for (int r = 0; r < count; ++r) fill_stats(h[(size_t)r], ms, &stats[r]);
+        }
+        return VR_OK;
+    });
+}
+
+}  // extern "C"

@@ -1,0 +1,157 @@
+// vr_dev.h — plain structs passed from host to the HIP kernels, and the
+// float-float ("double-single") arithmetic used for per-ray geometry.
+//
+// Ray set-up (camera ray, ray/box chord, sample-lattice anchors) runs in
+// float-float arithmetic: a value is an unevaluated sum hi + lo of two floats,
+// about 48 significant bits.  The error-free transformations are Knuth's
+// TwoSum, Dekker's Fast2Sum and the FMA-based TwoProduct (Dekker 1971;
+// Muller et al., Handbook of Floating-Point Arithmetic, ch. 4).  Per-sample
+// work stays in plain float on coordinates local to a brick, so every sample
+// position is accurate to a few 1e-6 voxel anywhere in a 2048^3 cube.
+#pragma once
+
+#include <stdint.h>
+
+struct ff {
+    float hi, lo;
+};
+
+// Limits shared with the host.
+#define VR_BRICK 32                 // brick edge (voxels)
+#define VR_BRICK_APRON 33           // stored edge: brick plus one apron voxel
+#define VR_CELL 8                   // skip-cell edge (voxels)
+#define VR_CELLS_PER_BRICK 64       // 4 x 4 x 4
+#define VR_TILE 16                  // workgroup tile edge (pixels)
+#define VR_WG 256                   // threads per workgroup (4 waves of 64)
+
+// Cube as seen by the render kernels.
+struct DevCube {
+    const uint8_t* pool;            // brick slots
+    const uint32_t* slot_of_brick;  // [bz][by][bx] -> slot
+    const uint64_t* mask;           // per slot: bit c set if cell c may contribute
+    uint64_t stride;                // bytes per slot
+    int32_t nx, ny, nz;
+    int32_t bx, by, bz;             // bricks per axis
+    int32_t dtype;                  // 0 f32, 1 f16, 2 bf16
+    int32_t pad;
+};
+
+// Transfer function: rows[2i] = row i (r, g, b, kappa), rows[2i+1] = row i+1 - row i.
+struct DevTf {
+    const float* rows;              // 8 floats per row
+    int32_t n;
+    float scale, bias;              // u = stored_value * scale + bias
+    float clip;                     // in stored units; -inf: none
+};
+
+// Camera constants in float-float.  Perspective: origin o, direction of pixel
+// (i, j) before normalisation base + (i+1/2) dx + (j+1/2) dy.  Orthographic:
+// origin o + (i+1/2) dx + (j+1/2) dy, direction dir.
+struct DevCam {
+    ff o[3], base[3], dx[3], dy[3], dir[3];
+    int32_t ortho;
+    int32_t pad;
+};
+
+// One render request (a whole image).
+struct DevReq {
+    DevCube cube;
+    DevTf tf;
+    DevCam cam;
+    float* out;                     // [H][W][4] (EA) or [H][W] (MIP)
+    int32_t W, H, tiles_x, tiles_y;
+    int32_t mode, interp, use_skip, pad;
+    ff step;                        // lattice spacing
+    float ert_T;                    // stop once transmittance <= ert_T
+    float out_scale;                // MIP: stored units -> data units
+};
+
+// Device counters (optional).
+struct DevCounters {
+    unsigned long long samples_nominal, samples_exec, rays_hit, rays_ert, cells_skipped, pad[3];
+};
+
+// One unit of batched work: a 16x16 tile of a request.
+struct DevItem {
+    int32_t req, tile;
+};
+
+#if defined(__HIPCC__) || defined(__HIP_DEVICE_COMPILE__)
+#define VR_FF_FN __device__ __forceinline__
+
+VR_FF_FN ff ff_make(float hi) { return ff{hi, 0.0f}; }
+
+VR_FF_FN ff two_sum(float a, float b) {
+#pragma clang fp contract(off)
+    float s = a + b;
+    float bb = s - a;
+    float e = (a - (s - bb)) + (b - bb);
+    return ff{s, e};
+}
+
+VR_FF_FN ff fast_two_sum(float a, float b) {
+#pragma clang fp contract(off)
+    float s = a + b;
+    float e = b - (s - a);
+    return ff{s, e};
+}
+
+VR_FF_FN ff two_prod(float a, float b) {
+#pragma clang fp contract(off)
+    float p = a * b;
+    float e = __builtin_fmaf(a, b, -p);
+    return ff{p, e};
+}
+
+VR_FF_FN ff ff_add(ff a, ff b) {
+#pragma clang fp contract(off)
+    ff s = two_sum(a.hi, b.hi);
+    ff t = two_sum(a.lo, b.lo);
+    s.lo += t.hi;
+    s = fast_two_sum(s.hi, s.lo);
+    s.lo += t.lo;
+    return fast_two_sum(s.hi, s.lo);
+}
+
+VR_FF_FN ff ff_neg(ff a) { return ff{-a.hi, -a.lo}; }
+VR_FF_FN ff ff_sub(ff a, ff b) { return ff_add(a, ff_neg(b)); }
+
+VR_FF_FN ff ff_mul(ff a, ff b) {
+#pragma clang fp contract(off)
+    ff p = two_prod(a.hi, b.hi);
+    p.lo = __builtin_fmaf(a.hi, b.lo, __builtin_fmaf(a.lo, b.hi, p.lo));
+    return fast_two_sum(p.hi, p.lo);
+}
+
+VR_FF_FN ff ff_mul_f(ff a, float b) {
+#pragma clang fp contract(off)
+    ff p = two_prod(a.hi, b);
+    p.lo = __builtin_fmaf(a.lo, b, p.lo);
+    return fast_two_sum(p.hi, p.lo);
+}
+
+VR_FF_FN ff ff_div(ff a, ff b) {
+#pragma clang fp contract(off)
+    float q1 = a.hi / b.hi;
+    ff r = ff_sub(a, ff_mul_f(b, q1));
+    float q2 = r.hi / b.hi;
+    r = ff_sub(r, ff_mul_f(b, q2));
+    float q3 = r.hi / b.hi;
+    ff q = fast_two_sum(q1, q2);
+    return ff_add(q, ff{q3, 0.0f});
+}
+
+VR_FF_FN ff ff_sqrt(ff a) {
+#pragma clang fp contract(off)
+    if (!(a.hi > 0.0f)) return ff{0.0f, 0.0f};
+    float s = __builtin_sqrtf(a.hi);
+    ff s2 = two_prod(s, s);
+    float r = ((a.hi - s2.hi) - s2.lo + a.lo) / (2.0f * s);
+    return fast_two_sum(s, r);
+}
+
+VR_FF_FN bool ff_lt(ff a, ff b) { return a.hi < b.hi || (a.hi == b.hi && a.lo < b.lo); }
+VR_FF_FN ff ff_min(ff a, ff b) { return ff_lt(b, a) ? b : a; }
+VR_FF_FN ff ff_max(ff a, ff b) { return ff_lt(a, b) ? b : a; }
+VR_FF_FN float ff_to_f(ff a) { return a.hi + a.lo; }
+#endif

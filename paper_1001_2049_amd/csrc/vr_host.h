@@ -1,0 +1,145 @@
+// vr_host.h — host-side objects behind the C interface (context, cubes,
+// transfer functions) and helpers shared by the API and the serving loop.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <atomic>
+#include <condition_variable>
+#include <cstdint>
+#include <deque>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <thread>
+#include <unordered_map>
+#include <vector>
+
+#include "../../include/vr.h"
+#include "vr_dev.h"
+
+namespace vrh {
+
+void set_error(const std::string& msg);
+
+struct Ctx;
+
+// Device memory owned by the library, allocated through the context's allocator.
+struct DevBuf {
+    void* ptr = nullptr;
+    uint64_t bytes = 0;
+};
+
+struct MaskEntry {
+    int mode = 0;
+    int64_t tf_version = -1;
+    uint32_t clip_bits = 0;
+    DevBuf buf;
+    hipEvent_t last_use = nullptr;  // last work reading this mask
+    uint64_t stamp = 0;
+};
+
+struct Cube {
+    vr_cube id = 0;
+    int64_t nx = 0, ny = 0, nz = 0;
+    int storage = VR_F32;
+    double sigma = 1.0;
+    int Bx = 0, By = 0, Bz = 0;
+    int nslots = 0;
+    uint64_t stride = 0;
+    DevBuf pool, slots, cellmm;
+    std::vector<MaskEntry> masks;
+    hipEvent_t last_use = nullptr;  // last work reading this cube
+    int refs = 0;                   // queued serving requests
+    uint64_t bytes() const;
+};
+
+struct Tf {
+    vr_tf id = 0;
+    int64_t version = 0;
+    int n = 0;
+    float v0 = 0.0f, v1 = 1.0f;
+    std::vector<float> rows;  // n x 4
+    DevBuf dev_rows;          // 2n float4: row, next row - row
+    DevBuf dev_kpos;          // n + 2 ints: prefix counts of kappa > 0
+    hipEvent_t last_use = nullptr;
+    bool internal = false;    // created by vr_set_transfer_function
+    int refs = 0;             // queued serving requests
+};
+
+struct Server;
+
+// Device and pinned staging for one persistent batched launch.
+struct BatchBufs {
+    DevBuf reqs, items, head;
+    DevReq* pin_reqs = nullptr;
+    DevItem* pin_items = nullptr;
+    int reqs_cap = 0, items_cap = 0;
+    hipEvent_t done = nullptr;  // staging is reusable once this has fired
+};
+
+struct Ctx {
+    int device = -1;
+    uint64_t budget = 0;
+    uint64_t used = 0;
+    bool has_alloc = false;
+    vr_allocator alloc{};
+    int num_cu = 256;
+    std::recursive_mutex mu;
+
+    // current state for vr_render
+    bool has_camera = false;
+    vr_camera camera{};
+    vr_tf current_tf = 0;
+    float clip = -__builtin_huge_valf();
+
+    std::map<vr_cube, std::unique_ptr<Cube>> cubes;
+    std::map<vr_tf, std::unique_ptr<Tf>> tfs;
+    int32_t next_cube = 1, next_tf = 1;
+    int64_t next_tf_version = 1;
+    uint64_t mask_stamp = 0;
+
+    // scratch for single renders / batches
+    DevBuf counters;             // DevCounters x capacity
+    int counters_cap = 0;
+    BatchBufs batch;
+
+    Server* server = nullptr;
+
+    bool host_only() const { return device < 0; }
+};
+
+// allocation through the context's allocator, counted against its budget
+vr_status dev_alloc(Ctx* c, DevBuf& b, uint64_t bytes, bool budgeted);
+void dev_free(Ctx* c, DevBuf& b, bool budgeted);
+
+vr_status hip_check(hipError_t e, const char* what);
+
+// validation helpers
+vr_status check_camera(const vr_camera* cam);
+vr_status check_params(const vr_render_params* p);
+vr_status check_tf(const float* rgbk, int32_t n, float v0, float v1);
+
+// camera constants for the kernels (float64 on the host, float-float to the device)
+void camera_setup(const vr_camera& cam, int W, int H, DevCam& out);
+
+// fill a DevReq for one image; classifies the skip mask on `s` if needed
+vr_status build_request(Ctx* c, Cube* cube, Tf* tf, float clip, const vr_camera& cam,
+                        const vr_render_params& p, void* out, hipStream_t s, DevReq& R,
+                        MaskEntry** mask_used);
+
+// mark objects used by work enqueued on s
+vr_status mark_use(Ctx* c, Cube* cube, Tf* tf, MaskEntry* mask, hipStream_t s);
+
+Cube* find_cube(Ctx* c, vr_cube id);
+Tf* find_tf(Ctx* c, vr_tf id);
+
+// one persistent launch over many requests (used by vr_render_batch and the server);
+// `tiles` optionally restricts request r to tiles [tiles[2r], tiles[2r+1])
+vr_status launch_requests(Ctx* c, BatchBufs& bb, const vr_request* reqs, int count,
+                          const int32_t* tiles, hipStream_t s, DevCounters* dev_counters);
+void free_batch_bufs(Ctx* c, BatchBufs& bb);
+vr_status check_request(Ctx* c, const vr_request* r);
+
+}  // namespace vrh
