@@ -139,10 +139,16 @@ typedef struct {
     uint64_t brick_stride;      /* bytes between brick slots */
     uint64_t aux_bytes;         /* device bytes of tables and statistics */
     float vmin, vmax;           /* range of stored values times sigma_scale */
+    int32_t row_elems;          /* stored elements per brick row (>= brick+1, 16-byte multiple) */
+    int32_t reserved;
     /* device pointers, for inspection: */
-    const void* pool;           /* brick slots, each (brick+1)^3 values, x fastest */
-    const uint32_t* slot_of_brick; /* [bricks_z][bricks_y][bricks_x] -> slot */
-    const float* cell_minmax;   /* per slot: 64 cells x (min, max) of stored values */
+    const void* pool;           /* brick slots; slot of brick (bx,by,bz) is
+                                   (bz*bricks_y + by)*bricks_x + bx; inside a slot, local
+                                   voxel (lx,ly,lz) in [0,brick]^3 is element
+                                   (lz*(brick+1) + ly)*row_elems + lx, edge-clamped */
+    const float* cell_minmax;   /* per slot: 64 cells x (min, max) of stored values; cell
+                                   (cx,cy,cz) in [0,3]^3 is entry (cz*4 + cy)*4 + cx and covers
+                                   local voxels [8c, 8c+8] per axis */
 } vr_cube_info;
 
 /* --- context ------------------------------------------------------------ */
@@ -170,7 +176,7 @@ const char* vr_version(void);
  * storage == src_dtype), in host memory (src_on_device = 0) or device memory
  * (1).  Float32 sources are converted to `storage` as round-to-nearest-even
  * of value/sigma_scale.  The cube is re-laid out into 32^3 bricks with a one-
- * voxel apron (Morton-ordered slots) and per-8^3-cell min/max tables
+ * voxel apron and per-8^3-cell min/max tables
  * (paper Sec. 3 process step 1: the cube is partitioned into sub-cubes).
  * Returns after src may be reused; the cube is ready for work on any stream
  * once this call returns. */

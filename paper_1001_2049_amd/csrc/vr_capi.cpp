@@ -23,8 +23,8 @@ vr_status hip_check(hipError_t e, const char* what) {
 }
 
 uint64_t Cube::bytes() const {
-    uint64_t b = pool.bytes + slots.bytes + cellmm.bytes;
-    for (const auto& m : masks) b += m.buf.bytes;
+    uint64_t b = pool.bytes + cellmm.bytes;
+    for (const auto& m : masks) b += m.buf.bytes + m.bits.bytes;
     return b;
 }
 
@@ -244,7 +244,11 @@ static vr_status get_mask(Ctx* c, Cube* cube, int mode, Tf* tf, float clip_s, hi
         cube->masks.emplace_back();
         e = &cube->masks.back();
         vr_status st = dev_alloc(c, e->buf, (uint64_t)cube->nslots * 8, true);
+        if (st == VR_OK)
+            st = dev_alloc(c, e->bits, (uint64_t)vr_cellbits_words(cube->Bx, cube->By, cube->Bz) * 4,
+                           true);
         if (st != VR_OK) {
+            dev_free(c, e->buf, true);
             cube->masks.pop_back();
             return st;
         }
@@ -267,9 +271,11 @@ static vr_status get_mask(Ctx* c, Cube* cube, int mode, Tf* tf, float clip_s, hi
         n = tf->n;
         kpos = (const int*)tf->dev_kpos.ptr;
     }
-    vr_status st = hip_check(vr_launch_classify((const float*)cube->cellmm.ptr, (uint64_t*)e->buf.ptr,
-                                                cube->nslots, mode, clip_s, scale, bias, n, kpos, s),
-                             "classify launch");
+    vr_status st = hip_check(
+        vr_launch_classify((const float*)cube->cellmm.ptr, (uint64_t*)e->buf.ptr,
+                           (uint32_t*)e->bits.ptr, cube->Bx, cube->By, cube->Bz, mode, clip_s, scale,
+                           bias, n, kpos, s),
+        "classify launch");
     if (st != VR_OK) return st;
     e->mode = mode;
     e->tf_version = ver;
@@ -292,8 +298,8 @@ vr_status build_request(Ctx* c, Cube* cube, Tf* tf, float clip, const vr_camera&
         return VR_EINVAL;
     }
     R.cube.pool = (const uint8_t*)cube->pool.ptr;
-    R.cube.slot_of_brick = (const uint32_t*)cube->slots.ptr;
     R.cube.stride = cube->stride;
+    R.cube.row = cube->row;
     R.cube.nx = (int)cube->nx;
     R.cube.ny = (int)cube->ny;
     R.cube.nz = (int)cube->nz;
@@ -316,8 +322,9 @@ vr_status build_request(Ctx* c, Cube* cube, Tf* tf, float clip, const vr_camera&
     R.out = (float*)out;
     R.W = p.width;
     R.H = p.height;
-    R.tiles_x = (p.width + VR_TILE - 1) / VR_TILE;
-    R.tiles_y = (p.height + VR_TILE - 1) / VR_TILE;
+    R.tiles_x = (p.width + VR_TW - 1) / VR_TW;
+    R.tiles_y = (p.height + VR_TH - 1) / VR_TH;
+    R.box_bytes = vr_box_bytes(p.mode == VR_EA ? tf->n : 0);
     R.mode = p.mode;
     R.interp = p.interp;
     R.use_skip = p.use_skip;
@@ -329,6 +336,7 @@ vr_status build_request(Ctx* c, Cube* cube, Tf* tf, float clip, const vr_camera&
         vr_status st = get_mask(c, cube, p.mode, tf, clip_s, s, &me);
         if (st != VR_OK) return st;
         R.cube.mask = (const uint64_t*)me->buf.ptr;
+        R.cube.cellbits = (const uint32_t*)me->bits.ptr;
         if (mask_used) *mask_used = me;
     }
     return VR_OK;
@@ -413,16 +421,27 @@ vr_status check_request(Ctx* c, const vr_request* r) {
 }
 
 void free_batch_bufs(Ctx* c, BatchBufs& bb) {
+    for (auto& kv : bb.graphs) (void)hipGraphExecDestroy(kv.second);
+    bb.graphs.clear();
     dev_free(c, bb.reqs, false);
     dev_free(c, bb.items, false);
     dev_free(c, bb.head, false);
+    dev_free(c, bb.hdr, false);
     if (bb.pin_reqs) (void)hipHostFree(bb.pin_reqs);
     if (bb.pin_items) (void)hipHostFree(bb.pin_items);
+    if (bb.pin_hdr) (void)hipHostFree(bb.pin_hdr);
     bb.pin_reqs = nullptr;
     bb.pin_items = nullptr;
+    bb.pin_hdr = nullptr;
     bb.reqs_cap = bb.items_cap = 0;
     if (bb.done) (void)hipEventDestroy(bb.done);
     bb.done = nullptr;
+}
+
+static int pow2_at_least(int v, int lo) {
+    int p = lo;
+    while (p < v) p <<= 1;
+    return p;
 }
 
 static vr_status grow_batch(Ctx* c, BatchBufs& bb, int nreq, int nitems) {
@@ -433,10 +452,14 @@ static vr_status grow_batch(Ctx* c, BatchBufs& bb, int nreq, int nitems) {
     if (st != VR_OK) return st;
     if (!bb.head.ptr) {
         st = dev_alloc(c, bb.head, 256, false);
+        if (st == VR_OK) st = dev_alloc(c, bb.hdr, 256, false);
+        if (st == VR_OK)
+            st = hip_check(hipHostMalloc((void**)&bb.pin_hdr, 256, 0), "hipHostMalloc");
         if (st != VR_OK) return st;
     }
+    bool regrown = false;
     if (bb.reqs_cap < nreq) {
-        int cap = std::max(nreq, 64);
+        const int cap = pow2_at_least(nreq, 64);
         dev_free(c, bb.reqs, false);
         if (bb.pin_reqs) (void)hipHostFree(bb.pin_reqs);
         bb.pin_reqs = nullptr;
@@ -447,9 +470,10 @@ static vr_status grow_batch(Ctx* c, BatchBufs& bb, int nreq, int nitems) {
                        "hipHostMalloc");
         if (st != VR_OK) return st;
         bb.reqs_cap = cap;
+        regrown = true;
     }
     if (bb.items_cap < nitems) {
-        int cap = std::max(nitems, 4096);
+        const int cap = pow2_at_least(nitems, 4096);
         dev_free(c, bb.items, false);
         if (bb.pin_items) (void)hipHostFree(bb.pin_items);
         bb.pin_items = nullptr;
@@ -460,16 +484,65 @@ static vr_status grow_batch(Ctx* c, BatchBufs& bb, int nreq, int nitems) {
                        "hipHostMalloc");
         if (st != VR_OK) return st;
         bb.items_cap = cap;
+        regrown = true;
+    }
+    if (regrown) {
+        // captured graphs point at the old buffers
+        for (auto& kv : bb.graphs) (void)hipGraphExecDestroy(kv.second);
+        bb.graphs.clear();
     }
     return VR_OK;
 }
 
+// copies + reset + batch kernel, either enqueued directly or captured once
+static vr_status enqueue_batch(Ctx* c, BatchBufs& bb, int count, int nitems, size_t lds,
+                               DevCounters* dev_counters, hipStream_t s, bool use_graph) {
+    const size_t rq_bytes = (size_t)(use_graph ? bb.reqs_cap : count) * sizeof(DevReq);
+    const size_t it_bytes = (size_t)(use_graph ? bb.items_cap : nitems) * sizeof(DevItem);
+    const int grid = use_graph ? c->num_cu : std::max(1, std::min(nitems, c->num_cu));
+    auto record = [&]() -> vr_status {
+        vr_status st = hip_check(hipMemcpyAsync(bb.hdr.ptr, bb.pin_hdr, 16, hipMemcpyHostToDevice, s),
+                                 "hipMemcpyAsync");
+        if (st == VR_OK)
+            st = hip_check(hipMemcpyAsync(bb.reqs.ptr, bb.pin_reqs, rq_bytes, hipMemcpyHostToDevice, s),
+                           "hipMemcpyAsync");
+        if (st == VR_OK)
+            st = hip_check(hipMemcpyAsync(bb.items.ptr, bb.pin_items, it_bytes, hipMemcpyHostToDevice, s),
+                           "hipMemcpyAsync");
+        if (st == VR_OK)
+            st = hip_check(vr_launch_batch((const DevReq*)bb.reqs.ptr, (const DevItem*)bb.items.ptr,
+                                           (const int*)bb.hdr.ptr, (unsigned*)bb.head.ptr,
+                                           dev_counters, lds, grid, s),
+                           "batch launch");
+        return st;
+    };
+    if (!use_graph) return record();
+    const uint64_t key = ((uint64_t)bb.items_cap << 40) ^ ((uint64_t)bb.reqs_cap << 24) ^ (uint64_t)lds;
+    auto it = bb.graphs.find(key);
+    if (it == bb.graphs.end()) {
+        vr_status st = hip_check(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal),
+                                 "hipStreamBeginCapture");
+        if (st != VR_OK) return st;
+        st = record();
+        hipGraph_t g = nullptr;
+        vr_status st2 = hip_check(hipStreamEndCapture(s, &g), "hipStreamEndCapture");
+        if (st == VR_OK) st = st2;
+        hipGraphExec_t ex = nullptr;
+        if (st == VR_OK) st = hip_check(hipGraphInstantiate(&ex, g, nullptr, nullptr, 0), "hipGraphInstantiate");
+        if (g) (void)hipGraphDestroy(g);
+        if (st != VR_OK) return st;
+        it = bb.graphs.emplace(key, ex).first;
+    }
+    return hip_check(hipGraphLaunch(it->second, s), "hipGraphLaunch");
+}
+
 vr_status launch_requests(Ctx* c, BatchBufs& bb, const vr_request* reqs, int count,
-                          const int32_t* tiles, hipStream_t s, DevCounters* dev_counters) {
+                          const int32_t* tiles, hipStream_t s, DevCounters* dev_counters,
+                          bool use_graph) {
     int nitems = 0;
     for (int r = 0; r < count; ++r) {
         const auto& p = reqs[r].params;
-        const int nt = ((p.width + VR_TILE - 1) / VR_TILE) * ((p.height + VR_TILE - 1) / VR_TILE);
+        const int nt = ((p.width + VR_TW - 1) / VR_TW) * ((p.height + VR_TH - 1) / VR_TH);
         nitems += tiles ? (tiles[2 * r + 1] - tiles[2 * r]) : nt;
     }
     vr_status st = grow_batch(c, bb, count, std::max(nitems, 1));
@@ -489,22 +562,13 @@ vr_status launch_requests(Ctx* c, BatchBufs& bb, const vr_request* reqs, int cou
         const int t1 = tiles ? tiles[2 * r + 1] : R.tiles_x * R.tiles_y;
         for (int t = t0; t < t1; ++t) bb.pin_items[k++] = DevItem{r, t};
     }
-    st = hip_check(hipMemcpyAsync(bb.reqs.ptr, bb.pin_reqs, (size_t)count * sizeof(DevReq),
-                                  hipMemcpyHostToDevice, s),
-                   "hipMemcpyAsync");
-    if (st != VR_OK) return st;
+    // shape class: the TF table size fixes the LDS split (256-row tables share one class)
+    if (use_graph) max_tf_n = std::max(max_tf_n, 256);
+    for (int r = 0; r < count; ++r) bb.pin_reqs[r].box_bytes = vr_box_bytes(max_tf_n);
+    bb.pin_hdr[0] = nitems;
     if (nitems > 0) {
-        st = hip_check(hipMemcpyAsync(bb.items.ptr, bb.pin_items, (size_t)nitems * sizeof(DevItem),
-                                      hipMemcpyHostToDevice, s),
-                       "hipMemcpyAsync");
-        if (st != VR_OK) return st;
-    }
-    const int grid = std::max(1, std::min(nitems, c->num_cu * 4));
-    if (nitems > 0) {
-        st = hip_check(vr_launch_batch((const DevReq*)bb.reqs.ptr, (const DevItem*)bb.items.ptr,
-                                       nitems, (unsigned*)bb.head.ptr, dev_counters, max_tf_n, grid,
-                                       s),
-                       "batch launch");
+        const size_t lds = (size_t)max_tf_n * 32 + 2 * (size_t)vr_box_bytes(max_tf_n);
+        st = enqueue_batch(c, bb, count, nitems, lds, dev_counters, s, use_graph);
         if (st != VR_OK) return st;
     }
     st = hip_check(hipEventRecord(bb.done, s), "hipEventRecord");
@@ -580,26 +644,13 @@ static vr_status release_cube(Ctx* c, Cube* cube) {
     }
     for (auto& m : cube->masks) {
         dev_free(c, m.buf, true);
+        dev_free(c, m.bits, true);
         if (m.last_use) (void)hipEventDestroy(m.last_use);
     }
     dev_free(c, cube->pool, true);
-    dev_free(c, cube->slots, true);
     dev_free(c, cube->cellmm, true);
     c->cubes.erase(cube->id);
     return VR_OK;
-}
-
-static uint64_t morton3(uint32_t x, uint32_t y, uint32_t z) {
-    auto spread = [](uint64_t v) {
-        v &= 0x1FFFFF;
-        v = (v | v << 32) & 0x1F00000000FFFFull;
-        v = (v | v << 16) & 0x1F0000FF0000FFull;
-        v = (v | v << 8) & 0x100F00F00F00F00Full;
-        v = (v | v << 4) & 0x10C30C30C30C30C3ull;
-        v = (v | v << 2) & 0x1249249249249249ull;
-        return v;
-    };
-    return spread(x) | (spread(y) << 1) | (spread(z) << 2);
 }
 
 }  // namespace vrh
@@ -754,36 +805,16 @@ vr_status vr_cube_upload(vr_ctx ctx, const void* src, int32_t src_dtype, int32_t
         }
         cube->nslots = (int)ns;
         const uint64_t elem = storage == VR_F32 ? 4 : 2;
-        cube->stride = (VR_BRICK_APRON * VR_BRICK_APRON * VR_BRICK_APRON * elem + 255) & ~uint64_t(255);
+        cube->row = VR_ROW(storage);
+        cube->stride =
+            ((uint64_t)VR_BRICK_APRON * VR_BRICK_APRON * cube->row * elem + 255) & ~uint64_t(255);
         auto cleanup = [&]() {
             dev_free(c, cube->pool, true);
-            dev_free(c, cube->slots, true);
             dev_free(c, cube->cellmm, true);
         };
         st = dev_alloc(c, cube->pool, (uint64_t)ns * cube->stride, true);
-        if (st == VR_OK) st = dev_alloc(c, cube->slots, (uint64_t)ns * 4, true);
         if (st == VR_OK)
             st = dev_alloc(c, cube->cellmm, (uint64_t)ns * 2 * VR_CELLS_PER_BRICK * 4, true);
-        if (st != VR_OK) {
-            cleanup();
-            return st;
-        }
-        // Morton-ordered slots
-        std::vector<uint32_t> order((size_t)ns);
-        std::iota(order.begin(), order.end(), 0u);
-        std::vector<uint64_t> code((size_t)ns);
-        for (int64_t b = 0; b < ns; ++b) {
-            const uint32_t bx = (uint32_t)(b % cube->Bx), by = (uint32_t)((b / cube->Bx) % cube->By),
-                           bz = (uint32_t)(b / ((int64_t)cube->Bx * cube->By));
-            code[(size_t)b] = morton3(bx, by, bz);
-        }
-        std::sort(order.begin(), order.end(),
-                  [&](uint32_t a, uint32_t b) { return code[a] < code[b]; });
-        std::vector<uint32_t> slot_of((size_t)ns);
-        for (int64_t r = 0; r < ns; ++r) slot_of[order[(size_t)r]] = (uint32_t)r;
-        st = hip_check(hipMemcpy(cube->slots.ptr, slot_of.data(), (size_t)ns * 4,
-                                 hipMemcpyHostToDevice),
-                       "hipMemcpy");
         if (st != VR_OK) {
             cleanup();
             return st;
@@ -813,9 +844,9 @@ vr_status vr_cube_upload(vr_ctx ctx, const void* src, int32_t src_dtype, int32_t
                 z_first = z0;
             }
             st = hip_check(vr_launch_brick_build(src_kind, storage, slab, nx, ny, nz, z_first, bz,
-                                                 cube->Bx, cube->By, (const uint32_t*)cube->slots.ptr,
-                                                 (uint8_t*)cube->pool.ptr, cube->stride,
-                                                 (float*)cube->cellmm.ptr, (float)sigma_scale, s),
+                                                 cube->Bx, cube->By, (uint8_t*)cube->pool.ptr,
+                                                 cube->stride, cube->row, (float*)cube->cellmm.ptr,
+                                                 (float)sigma_scale, s),
                            "brick build launch");
         }
         vr_status st2 = hip_check(hipStreamSynchronize(s), "hipStreamSynchronize");
@@ -882,7 +913,7 @@ vr_status vr_cube_get_info(vr_ctx ctx, vr_cube cube, vr_cube_info* out) {
         out->brick_stride = cu->stride;
         out->aux_bytes = cu->bytes() - cu->pool.bytes;
         out->pool = cu->pool.ptr;
-        out->slot_of_brick = (const uint32_t*)cu->slots.ptr;
+        out->row_elems = cu->row;
         out->cell_minmax = (const float*)cu->cellmm.ptr;
         (void)hipSetDevice(c->device);
         std::vector<float> mm((size_t)cu->nslots * 2 * VR_CELLS_PER_BRICK);
@@ -1072,6 +1103,10 @@ vr_status vr_tf_release(vr_ctx ctx, vr_tf tf) {
         }
         if (tf == c->current_tf) {
             set_error("the context's current transfer function cannot be released");
+            return VR_EBUSY;
+        }
+        if (t->refs > 0) {
+            set_error("transfer function is referenced by queued requests");
             return VR_EBUSY;
         }
         if (!c->host_only()) (void)hipSetDevice(c->device);

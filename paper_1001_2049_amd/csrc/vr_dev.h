@@ -16,24 +16,36 @@ struct ff {
     float hi, lo;
 };
 
-// Limits shared with the host.
+// Layout and launch shape shared with the host.
 #define VR_BRICK 32                 // brick edge (voxels)
 #define VR_BRICK_APRON 33           // stored edge: brick plus one apron voxel
 #define VR_CELL 8                   // skip-cell edge (voxels)
 #define VR_CELLS_PER_BRICK 64       // 4 x 4 x 4
-#define VR_TILE 16                  // workgroup tile edge (pixels)
-#define VR_WG 256                   // threads per workgroup (4 waves of 64)
+#define VR_TW 32                    // workgroup tile width (pixels)
+#define VR_TH 16                    // workgroup tile height (pixels)
+#define VR_WG 512                   // threads per render workgroup (8 waves of 64)
+#define VR_NWAVE (VR_WG / 64)
+#define VR_LDS_MAX 163840           // LDS per workgroup on gfx950
+#define VR_LDS_STATIC 4096          // reserved for the kernels' static LDS
+// Stored rows are padded to a multiple of 16 bytes so that any 16-byte chunk
+// starting at a local x that is a multiple of 4 (float) or 8 (16-bit) stays in
+// its row and is 16-byte aligned.
+#define VR_ROW_F32 36
+#define VR_ROW_16 40
+#define VR_ROW(dt) ((dt) == 0 ? VR_ROW_F32 : VR_ROW_16)
 
-// Cube as seen by the render kernels.
+// Cube as seen by the render kernels.  Slot of brick (bx, by, bz) is the
+// linear index (bz * by_count + by) * bx_count + bx; voxel (lx, ly, lz) of a
+// slot sits at element (lz * 33 + ly) * row + lx.
 struct DevCube {
     const uint8_t* pool;            // brick slots
-    const uint32_t* slot_of_brick;  // [bz][by][bx] -> slot
     const uint64_t* mask;           // per slot: bit c set if cell c may contribute
+    const uint32_t* cellbits;       // per cell (x fastest, 4 cells per brick edge): may contribute
     uint64_t stride;                // bytes per slot
     int32_t nx, ny, nz;
     int32_t bx, by, bz;             // bricks per axis
     int32_t dtype;                  // 0 f32, 1 f16, 2 bf16
-    int32_t pad;
+    int32_t row;                    // elements per stored row
 };
 
 // Transfer function: rows[2i] = row i (r, g, b, kappa), rows[2i+1] = row i+1 - row i.
@@ -60,7 +72,8 @@ struct DevReq {
     DevCam cam;
     float* out;                     // [H][W][4] (EA) or [H][W] (MIP)
     int32_t W, H, tiles_x, tiles_y;
-    int32_t mode, interp, use_skip, pad;
+    int32_t mode, interp, use_skip;
+    int32_t box_bytes;              // LDS bytes of one slab box buffer (two are used)
     ff step;                        // lattice spacing
     float ert_T;                    // stop once transmittance <= ert_T
     float out_scale;                // MIP: stored units -> data units
@@ -71,7 +84,7 @@ struct DevCounters {
     unsigned long long samples_nominal, samples_exec, rays_hit, rays_ert, cells_skipped, pad[3];
 };
 
-// One unit of batched work: a 16x16 tile of a request.
+// One unit of batched work: one workgroup tile of a request.
 struct DevItem {
     int32_t req, tile;
 };
@@ -151,7 +164,14 @@ VR_FF_FN ff ff_sqrt(ff a) {
 }
 
 VR_FF_FN bool ff_lt(ff a, ff b) { return a.hi < b.hi || (a.hi == b.hi && a.lo < b.lo); }
-VR_FF_FN ff ff_min(ff a, ff b) { return ff_lt(b, a) ? b : a; }
-VR_FF_FN ff ff_max(ff a, ff b) { return ff_lt(a, b) ? b : a; }
+// field-wise selects: a select of whole structs would go through stack memory
+VR_FF_FN ff ff_sel(bool c, ff a, ff b) {
+    ff r;
+    r.hi = c ? a.hi : b.hi;
+    r.lo = c ? a.lo : b.lo;
+    return r;
+}
+VR_FF_FN ff ff_min(ff a, ff b) { return ff_sel(ff_lt(b, a), b, a); }
+VR_FF_FN ff ff_max(ff a, ff b) { return ff_sel(ff_lt(a, b), b, a); }
 VR_FF_FN float ff_to_f(ff a) { return a.hi + a.lo; }
 #endif

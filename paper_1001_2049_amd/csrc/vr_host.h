@@ -35,7 +35,8 @@ struct MaskEntry {
     int mode = 0;
     int64_t tf_version = -1;
     uint32_t clip_bits = 0;
-    DevBuf buf;
+    DevBuf buf;                     // per slot 64-bit masks
+    DevBuf bits;                    // per-cell grid
     hipEvent_t last_use = nullptr;  // last work reading this mask
     uint64_t stamp = 0;
 };
@@ -47,8 +48,9 @@ struct Cube {
     double sigma = 1.0;
     int Bx = 0, By = 0, Bz = 0;
     int nslots = 0;
+    int row = 0;                    // elements per stored row
     uint64_t stride = 0;
-    DevBuf pool, slots, cellmm;
+    DevBuf pool, cellmm;
     std::vector<MaskEntry> masks;
     hipEvent_t last_use = nullptr;  // last work reading this cube
     int refs = 0;                   // queued serving requests
@@ -70,13 +72,16 @@ struct Tf {
 
 struct Server;
 
-// Device and pinned staging for one persistent batched launch.
+// Device and pinned staging for one persistent batched launch, and the
+// graphs captured over those buffers (one per shape class).
 struct BatchBufs {
-    DevBuf reqs, items, head;
+    DevBuf reqs, items, head, hdr;
     DevReq* pin_reqs = nullptr;
     DevItem* pin_items = nullptr;
+    int* pin_hdr = nullptr;
     int reqs_cap = 0, items_cap = 0;
     hipEvent_t done = nullptr;  // staging is reusable once this has fired
+    std::map<uint64_t, hipGraphExec_t> graphs;  // key: (items class, requests class, LDS bytes)
 };
 
 struct Ctx {
@@ -106,6 +111,7 @@ struct Ctx {
     BatchBufs batch;
 
     Server* server = nullptr;
+    std::mutex server_mu;       // guards server start/stop
 
     bool host_only() const { return device < 0; }
 };
@@ -136,9 +142,12 @@ Cube* find_cube(Ctx* c, vr_cube id);
 Tf* find_tf(Ctx* c, vr_tf id);
 
 // one persistent launch over many requests (used by vr_render_batch and the server);
-// `tiles` optionally restricts request r to tiles [tiles[2r], tiles[2r+1])
+// `tiles` optionally restricts request r to tiles [tiles[2r], tiles[2r+1]).  With
+// use_graph the copies and kernels are replayed from a graph captured per
+// shape class (stream s must not be the null stream).
 vr_status launch_requests(Ctx* c, BatchBufs& bb, const vr_request* reqs, int count,
-                          const int32_t* tiles, hipStream_t s, DevCounters* dev_counters);
+                          const int32_t* tiles, hipStream_t s, DevCounters* dev_counters,
+                          bool use_graph = false);
 void free_batch_bufs(Ctx* c, BatchBufs& bb);
 vr_status check_request(Ctx* c, const vr_request* r);
 

@@ -6,21 +6,36 @@
 
 #include "vr_dev.h"
 
+// words of the per-cell skip grid (4 cells per brick edge)
+inline int vr_cellbits_words(int Bx, int By, int Bz) {
+    const int64_t cells = (int64_t)64 * Bx * By * Bz;
+    return (int)((cells + 31) / 32);
+}
+
+// LDS bytes of one slab box buffer for a transfer function of n rows (0: MIP)
+inline int vr_box_bytes(int tf_rows) {
+    const int avail = (VR_LDS_MAX - VR_LDS_STATIC - 32 * tf_rows) / 2;
+    const int b = (avail / 16) * 16;
+    return b < 73728 ? b : 73728;
+}
+
 // Build the bricks of brick layer bz from a linear slab whose first plane is
 // z_first.  src_kind: 0 float32 values, 1/2 16-bit codes stored as-is.
 hipError_t vr_launch_brick_build(int src_kind, int dst, const void* src, int64_t nx, int64_t ny,
                                  int64_t nz, int64_t z_first, int bz, int Bx, int By,
-                                 const uint32_t* slot_of_brick, uint8_t* pool, uint64_t stride,
-                                 float* cell_minmax, float sigma, hipStream_t s);
+                                 uint8_t* pool, uint64_t stride, int row, float* cell_minmax,
+                                 float sigma, hipStream_t s);
 
-// Per-slot skip masks for one (mode, transfer function, clip) classification.
-hipError_t vr_launch_classify(const float* cell_minmax, uint64_t* mask, int nslots, int mode,
-                              float clip, float scale, float bias, int n, const int* kpos,
-                              hipStream_t s);
+// Skip masks (per slot) and the per-cell grid for one (mode, transfer function, clip).
+hipError_t vr_launch_classify(const float* cell_minmax, uint64_t* mask, uint32_t* cellbits,
+                              int Bx, int By, int Bz, int mode, float clip, float scale,
+                              float bias, int n, const int* kpos, hipStream_t s);
 
-// One image, one workgroup per 16x16 tile.
+// One image, one workgroup per 32x16 tile.
 hipError_t vr_launch_render(const DevReq& R, DevCounters* cnt, hipStream_t s);
 
-// Many images in one persistent launch over a (request, tile) work list.
-hipError_t vr_launch_batch(const DevReq* reqs, const DevItem* items, int nitems, unsigned* head,
-                           DevCounters* cnt, int max_tf_n, int grid, hipStream_t s);
+// Many images in one persistent launch over a (request, tile) work list of
+// *nitems entries (read on the device, so a captured launch serves any count).
+hipError_t vr_launch_batch(const DevReq* reqs, const DevItem* items, const int* nitems,
+                           unsigned* head, DevCounters* cnt, size_t lds_bytes, int grid,
+                           hipStream_t s);
