@@ -59,6 +59,105 @@ def cpu_baseline(vol, tf, wl, cams, W, H, mode, budget_s=12.0, max_views=4):
                       % (nviews, W, H, nviews - 1, t_all)}
 
 
+def serving_leg(n_requests=256, load=0.7, seed=4242):
+    """Serving form: 8 device-resident FP16 cubes (sizes drawn per axis from
+    128..1024 x 128..1024 x 128..512, noise plus density-matched sources),
+    view requests with random orbit cameras, image sizes {256, 512, 1024, 2048}^2
+    and EA/MIP 50/50, served with continuous batching.  First a closed loop
+    (all requests at once) gives the saturation throughput; then requests
+    arrive as a Poisson process at `load` x that rate and the server-side
+    latency (arrival to completion) is reported as p50/p99."""
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_1001_2049_amd import Renderer
+
+    r = Renderer(0)
+    specs = synth.serving_cubes(8)
+    cubes, t_gen = [], 0.0
+    for sp in specs:
+        t0 = time.perf_counter()
+        vol = synth.cube(sp, threads=cpu_threads())
+        t_gen += time.perf_counter() - t0
+        cubes.append(r.upload(vol, "f16"))
+        del vol
+    log("serving: 8 cubes generated in %.1f s and uploaded" % t_gen)
+    tf = synth.ramp_tf(256, 1.0)
+    r.set_transfer_function(tf, 3.0, 50.0)
+    r.set_noise_clip(3.0, 1.0)
+    rng = np.random.default_rng(seed)
+    sizes = [256, 512, 1024, 2048]
+    reqs, outs, meta = [], [], []
+    for i in range(n_requests):
+        ci = int(rng.integers(0, 8))
+        sz = sizes[int(rng.integers(0, 4))]
+        mode = "ea" if rng.random() < 0.5 else "mip"
+        sp = specs[ci]
+        cam = synth.orbit_camera(sp.nx, sp.ny, sp.nz, float(rng.uniform(0, 2 * math.pi)),
+                                 float(rng.uniform(-math.pi / 4, math.pi / 4)))
+        out = r.output(sz, sz, mode)
+        reqs.append(r.request(cubes[ci], cam, sz, sz, out, mode=mode, clip=3.0))
+        outs.append(out)
+        meta.append((ci, sz, mode, cam))
+    # nominal samples per request (untimed pass with counters)
+    nominal = []
+    for k in range(0, n_requests, 32):
+        nominal += [st["samples_nominal"] for st in r.render_batch(reqs[k:k + 32], stats=True)]
+    torch.cuda.synchronize()
+    total = float(sum(nominal))
+    # the plain renderer, one request after another
+    t0 = time.perf_counter()
+    for (ci, sz, mode, cam), out in zip(meta, outs):
+        r.set_camera(cam)
+        r.render(cubes[ci], sz, sz, mode=mode, out=out)
+    torch.cuda.synchronize()
+    t_plain = time.perf_counter() - t0
+    r.server_start(max_batch_requests=64, max_batch_tiles=4096, max_inflight=2, use_graphs=1)
+    try:
+        # warm-up (graph capture per shape class), then saturation
+        for t in [r.submit(q) for q in reqs[:32]]:
+            r.wait(t, timeout_s=60)
+        t0 = time.perf_counter()
+        tickets = [r.submit(q) for q in reqs]
+        for t in tickets:
+            r.wait(t, timeout_s=120)
+        t_sat = time.perf_counter() - t0
+        rate_sat = n_requests / t_sat
+        lam = load * rate_sat
+        gaps = rng.exponential(1.0 / lam, size=n_requests)
+        t0 = time.perf_counter()
+        t_next = t0
+        tickets = []
+        for q, g in zip(reqs, gaps):
+            t_next += g
+            d = t_next - time.perf_counter()
+            if d > 0:
+                time.sleep(d)
+            tickets.append(r.submit(q))
+        lat = [r.wait(t, timeout_s=120) for t in tickets]
+        t_open = time.perf_counter() - t0
+    finally:
+        r.server_stop()
+    r.close()
+    lat_ms = np.asarray(lat) * 1e3
+    return {
+        "requests": n_requests,
+        "cubes": [[sp.nx, sp.ny, sp.nz] for sp in specs],
+        "storage": "f16",
+        "samples_total": total,
+        "saturation_requests_per_s": round(rate_sat, 2),
+        "saturation_gsamples_per_s": round(total / t_sat / 1e9, 3),
+        "plain_sequential_gsamples_per_s": round(total / t_plain / 1e9, 3),
+        "poisson_load": load,
+        "poisson_rate_per_s": round(lam, 2),
+        "latency_ms_p50": round(float(np.percentile(lat_ms, 50)), 3),
+        "latency_ms_p99": round(float(np.percentile(lat_ms, 99)), 3),
+        "latency_ms_max": round(float(lat_ms.max()), 3),
+        "open_loop_gsamples_per_s": round(total / t_open / 1e9, 3),
+    }
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -69,10 +168,12 @@ def main():
     ap.add_argument("--size", type=int, default=1024, help="image width = height")
     ap.add_argument("--no-skip", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--serving-requests", type=int, default=256)
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only (--gpus %d requested); the renderer has no "
-              "multi-GPU path in this build" % args.gpus, file=sys.stderr)
+              "multi-GPU path" % args.gpus, file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
@@ -186,6 +287,10 @@ def main():
         log("timing the CPU reference")
         res["cpu_baseline"] = cpu_baseline(vol, tf, wl, cams, W, H, args.mode)
     r.close()
+    del r
+    if not args.no_serving:
+        log("serving leg")
+        res["serving"] = serving_leg(args.serving_requests)
     print(json.dumps(res), flush=True)
 
 

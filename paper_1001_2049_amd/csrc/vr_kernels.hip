@@ -352,6 +352,28 @@ __device__ __forceinline__ float interp_at(P bp, int sy, int sz, float w0, float
     return Vox<DT>::dec(bp[0]);
 }
 
+// Value at element idx of a box staged in LDS, strides (1, sy, sz) elements.
+// 16-bit storage: the pair (x, x+1) is cut from the two aligned dwords that
+// hold it (row strides are multiples of 8 elements, so every row shares the
+// parity of idx), keeping every LDS access dword-aligned.
+template <int DT, int INTERP>
+__device__ __forceinline__ float interp_box(__attribute__((address_space(3))) const typename Vox<DT>::T* box,
+                                            int idx, int sy, int sz, float w0, float w1, float w2) {
+    if (DT == 0 || INTERP == 0) return interp_at<DT, INTERP>(box + idx, sy, sz, w0, w1, w2);
+    typedef __attribute__((address_space(3))) const uint32_t LW;
+    LW* wp = (LW*)box + (idx >> 1);
+    const uint32_t sel = (idx & 1) ? 0x05040302u : 0x03020100u;
+    const int hy = sy >> 1, hz = sz >> 1;
+    const uint32_t p00 = __builtin_amdgcn_perm(wp[1], wp[0], sel);
+    const uint32_t p10 = __builtin_amdgcn_perm(wp[hy + 1], wp[hy], sel);
+    const uint32_t p01 = __builtin_amdgcn_perm(wp[hz + 1], wp[hz], sel);
+    const uint32_t p11 = __builtin_amdgcn_perm(wp[hz + hy + 1], wp[hz + hy], sel);
+    return trilerp(Vox<DT>::dec((uint16_t)p00), Vox<DT>::dec((uint16_t)(p00 >> 16)),
+                   Vox<DT>::dec((uint16_t)p10), Vox<DT>::dec((uint16_t)(p10 >> 16)),
+                   Vox<DT>::dec((uint16_t)p01), Vox<DT>::dec((uint16_t)(p01 >> 16)),
+                   Vox<DT>::dec((uint16_t)p11), Vox<DT>::dec((uint16_t)(p11 >> 16)), w0, w1, w2);
+}
+
 // Accumulation state of one ray.
 struct Accum {
     float C0, C1, C2, T, m;
@@ -530,30 +552,25 @@ __device__ __forceinline__ void render_lane_direct(const DevReq& R, const int px
 // Slab-staged tile renderer (the main path).
 //
 // A 512-thread workgroup owns a 32x16 pixel tile and marches all its rays in
-// lock-step through slabs S voxels thick along the major axis M of the tile's
-// view direction, front to back.  For each slab it reduces the range of voxel
-// indices its samples touch (a box), tests the box's 8^3 cells against the
-// skip grid, copies the box into LDS with 16-byte global->LDS DMA, and every
-// lane then interpolates its ray's samples in that slab from LDS.  Two box
-// buffers and a two-slab lookahead let the copy of slab k+1 and the skip-grid
-// reads of slab k+2 run while slab k is sampled; each slab costs one barrier.
-// A box larger than its buffer is sampled straight from the brick pool with
-// the same arithmetic, so the image never depends on staging decisions.
+// lock-step through slabs along the major axis M of the tile's view direction,
+// front to back.  Every ray of the tile passes, at any plane perpendicular to
+// M, inside the quadrilateral cut by the tile's four corner rays (the tile's
+// rays form a pyramid, or a prism for orthographic views), so the box of voxel
+// indices the samples of a slab can touch follows from the corner rays alone.
+// Each slab's thickness is the largest power of two up to 32 whose box fits a
+// fixed reference size; that choice depends only on the tile's geometry, so
+// the image never depends on staging decisions, batch composition or the LDS
+// the caller leaves free.  The box's 8^3 cells are tested against the skip
+// grid two slabs ahead, the box of the next slab is copied into LDS with
+// 16-byte global->LDS loads while the current slab is sampled, and every lane
+// interpolates its ray's samples of the slab from LDS.  A box larger than its
+// buffer is sampled straight from the brick pool with the same arithmetic.
 // ---------------------------------------------------------------------------
-#define VR_RING 5
 #define VR_BIG 0x3fffffff
+#define VR_SMAX 32
+// boxes are sized against this many bytes whatever LDS is actually free
+#define VR_BOX_REF 73728
 
-struct SlabDesc {
-    int bmin[3], bmax[3];  // sample floor range, relative to the slab origin
-    int any;               // some cell of the box may contribute
-    int pad;
-};
-
-struct TileShared {
-    int red[12];           // tile-start reductions
-    SlabDesc d[VR_RING];   // slab descriptors, ring indexed by slab % VR_RING
-    int alive[3];          // rays still marching after slab k, ring by k % 3
-};
 
 __device__ __forceinline__ int wave_min(int v) {
 #pragma unroll
@@ -591,73 +608,150 @@ __device__ __forceinline__ int div_small(int i, int d, float inv_d) {
     return q;
 }
 
-// Geometry of slab k that every lane derives identically.
-template <int M>
-struct SlabGeo {
-    int B0[3];     // integer origin of the slab's local coordinates
-    float zexit;   // plane the rays cross when leaving the slab
+// The tile's corner rays as lines over the major axis: on the plane M = z the
+// corner ray k sits at lateral coordinate c[k][q] + z * r[k][q] (q = 0 for axis
+// (M+1)%3, 1 for (M+2)%3).
+struct Corners {
+    float c[4][2], r[4][2];
 };
 
-template <int M>
-__device__ __forceinline__ SlabGeo<M> slab_geo(int k, int Z0, int S, int sgn, const float* rf,
-                                               const float* cf) {
+// One slab: planes [z0, z0 + S] along M, and the box of voxel indices its
+// samples can touch (floor indices plus the +1 neighbour), clamped to the cube.
+struct Slab {
+    int z0, S;
+    int lo[3], dim[3];
+    int xa, nc;   // first 16-byte-aligned x of the box, 16-byte chunks of data per box row
+    int np;       // chunks per LDS row: nc, rounded up to odd from 3 chunks on so
+                  // that consecutive rows start on different LDS banks
+    int elems;    // LDS elements of the box (row pitch np * chunk), 0 if empty
+    int big;      // the box takes both LDS buffers
+    int boff;     // byte offset of the box in the LDS box area
+    int late;     // copied only after the previous slab is sampled (it or the
+                  // previous slab takes both buffers)
+};
+
+struct TileShared {
+    int red[4];    // tile-start reductions: first/last sample planes
+    int any[8];    // slab k may contribute (skip grid), ring by k % 8
+    int alive[3];  // some ray still marching after slab k, ring by k % 3
+    Slab ring[4];  // slab k's geometry, ring by k % 4 (S == 0: no such slab)
+};
+
+template <int M, int CV>
+__device__ __forceinline__ Slab slab_box(int z0, int S, const Corners& cr, const int N[3],
+                                         int zmin, int zmax) {
     constexpr int A1 = (M + 1) % 3, A2 = (M + 2) % 3;
-    SlabGeo<M> g;
-    const int zlow = sgn > 0 ? Z0 + S * k : Z0 - S * (k + 1);
-    g.zexit = (float)(sgn > 0 ? zlow + S : zlow);
-    const float zmid = (float)zlow + 0.5f * (float)S;
-    g.B0[M] = zlow;
-    g.B0[A1] = (int)floorf(__builtin_fmaf(zmid, rf[A1], cf[A1]));
-    g.B0[A2] = (int)floorf(__builtin_fmaf(zmid, rf[A2], cf[A2]));
-    return g;
-}
-
-// Samples [k0, k1) of one ray in a slab with origin B0: local anchor and clamp bounds.
-__device__ __forceinline__ void slab_anchor(const DevReq& R, const Ray& ray, int k0,
-                                            const int B0[3], float A[3], float lo[3], float hi[3]) {
-    const int N[3] = {R.cube.nx, R.cube.ny, R.cube.nz};
-    const ff t0 = sample_t(R, ray, k0);
+    Slab s;
+    s.z0 = z0;
+    s.S = S;
+    // samples of the slab lie on [z0, z0 + S] along M up to rounding; at the
+    // cube's faces they can also lie in [-1/2, 0) or (N - 1, N - 1/2]
+    float za = z0 <= 0 ? -0.5f : (float)z0;
+    float zb = z0 + S >= N[M] - 1 ? (float)N[M] - 0.5f : (float)(z0 + S);
+    za -= 1e-3f;
+    zb += 1e-3f;
+    int lo[3], hi[3];
+    lo[M] = max(max(z0 - 1, zmin - 1), 0);
+    hi[M] = min(min(z0 + S, zmax + 1), N[M] - 1);
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+        const int a = q == 0 ? A1 : A2;
+        float mn = VR_INF, mx = -VR_INF;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const float v0 = __builtin_fmaf(za, cr.r[k][q], cr.c[k][q]);
+            const float v1 = __builtin_fmaf(zb, cr.r[k][q], cr.c[k][q]);
+            mn = fminf(mn, fminf(v0, v1));
+            mx = fmaxf(mx, fmaxf(v0, v1));
+        }
+        lo[a] = max((int)floorf(mn - 0.01f), 0);
+        hi[a] = min((int)floorf(mx + 0.01f), N[a] - 1);
+    }
+    bool empty = false;
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
-        A[a] = ff_to_f(ff_add(ff_add(ray.o[a], ff_mul(t0, ray.d[a])), ff_make(-(float)B0[a])));
-        lo[a] = (float)(-B0[a]);
-        hi[a] = (float)(N[a] - 1 - B0[a]);
+        s.lo[a] = lo[a];
+        s.dim[a] = hi[a] - lo[a] + 2;
+        empty = empty || hi[a] < lo[a];
     }
+    s.xa = lo[0] & ~(CV - 1);
+    s.nc = (lo[0] + s.dim[0] - 1 - s.xa) / CV + 1;
+    s.np = s.nc >= 3 ? (s.nc | 1) : s.nc;
+    s.big = 0;
+    s.boff = 0;
+    s.late = 0;
+    s.elems = empty ? 0 : s.np * CV * s.dim[1] * s.dim[2];
+    return s;
 }
 
-// Derived box geometry of a reduced slab descriptor.
-struct BoxGeo {
-    int blo[3], bdim[3], g0[3];
-    int xa, nc, pitch, elems;
-    bool empty;
-};
-
-template <int DT, int INTERP>
-__device__ __forceinline__ BoxGeo box_geo(const SlabDesc& d, const int B0[3]) {
-    constexpr int CV = DT == 0 ? 4 : 8;
-    BoxGeo b;
-    b.empty = d.bmin[0] > d.bmax[0];
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-        b.blo[a] = d.bmin[a];
-        b.bdim[a] = d.bmax[a] - d.bmin[a] + 1 + (INTERP == 1 ? 1 : 0);
-        b.g0[a] = B0[a] + b.blo[a];
+// Thickest slab entered at plane ze, at most hi voxels, whose box holds at
+// most cap elements (bisection: the box only grows with the thickness);
+// ok = false when not even one voxel fits.
+template <int M, int CV>
+__device__ __forceinline__ Slab fit_slab(int ze, int sgn, int hi, int cap, const Corners& cr,
+                                         const int N[3], int zmin, int zmax, bool& ok) {
+    Slab best = slab_box<M, CV>(sgn > 0 ? ze : ze - hi, hi, cr, N, zmin, zmax);
+    ok = true;
+    if (best.elems <= cap) return best;
+    int lo = 0;  // thickest known to fit (0: none); hi never fits
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        const Slab m = slab_box<M, CV>(sgn > 0 ? ze : ze - mid, mid, cr, N, zmin, zmax);
+        if (m.elems <= cap) {
+            lo = mid;
+            best = m;
+        } else {
+            hi = mid;
+        }
     }
-    b.xa = b.g0[0] & ~(CV - 1);
-    b.nc = (b.g0[0] + b.bdim[0] - 1 - b.xa) / CV + 1;
-    b.pitch = b.nc * CV;
-    b.elems = b.empty ? 0 : b.pitch * b.bdim[1] * b.bdim[2];
-    return b;
+    ok = lo > 0;
+    return best;
+}
+
+// Next slab entered at plane ze.  Normally the thickest (at most twice the
+// previous thickness and VR_SMAX) whose box fits one LDS buffer of the
+// reference size, so that its copy overlaps the sampling of the slab before.
+// When that is thinner than 2 voxels, the thickest (at most 8) whose box fits
+// both buffers is taken instead and copied after the slab before it has been
+// sampled.  A box that fits neither, even one voxel thick, is marched 8 voxels
+// at a time from the brick pool.  Only geometry decides, never the LDS a
+// launch actually has.
+template <int M, int CV, int ELEM>
+__device__ __forceinline__ Slab next_slab(int ze, int sgn, int Sprev, const Corners& cr,
+                                          const int N[3], int zmin, int zmax) {
+    constexpr int cap = VR_BOX_REF / ELEM;
+    bool ok;
+    Slab s = fit_slab<M, CV>(ze, sgn, min(VR_SMAX, 2 * Sprev), cap, cr, N, zmin, zmax, ok);
+    if (ok && s.S >= 2) return s;
+    bool okb;
+    Slab b = fit_slab<M, CV>(ze, sgn, 8, 2 * cap, cr, N, zmin, zmax, okb);
+    if (okb) {
+        b.big = 1;
+        return b;
+    }
+    return slab_box<M, CV>(sgn > 0 ? ze : ze - 8, 8, cr, N, zmin, zmax);
+}
+
+// Anchor of lattice sample k0 (without the last segment's shift) relative to
+// the integer point lo on one axis: E + (k0 + 1/2) step d - lo, with E the
+// ray's entry point, evaluated in float-float and rounded once.
+__device__ __forceinline__ float anchor_axis(const ff& E, const ff& d, const ff& sk, int lo) {
+#pragma clang fp contract(off)
+    ff h = two_sum(E.hi, -(float)lo);
+    h.lo += E.lo;
+    const ff p = ff_mul(sk, d);
+    const ff q = two_sum(h.hi, p.hi);
+    return q.hi + (q.lo + (h.lo + p.lo));
 }
 
 template <int MODE, int DT, int INTERP, int M>
 __device__ __forceinline__ bool tile_march(const DevReq& R, const Ray& ray, const int px,
-                                           const int py, const bool inimg, const ff* oc,
-                                           const ff* dc, const int sgn,
-                                           const float* __restrict__ tfl, uint8_t* __restrict__ boxes,
-                                           TileShared& sh, LaneCounts& cnt) {
+                                           const int py, const bool inimg, const Corners& cr,
+                                           const int sgn, const float* __restrict__ tfl,
+                                           uint8_t* __restrict__ boxes, TileShared& sh,
+                                           LaneCounts& cnt) {
     typedef typename Vox<DT>::T VT;
-    constexpr int A1 = (M + 1) % 3, A2 = (M + 2) % 3;
+    typedef __attribute__((address_space(3))) const VT LVT;
     constexpr int ELEM = DT == 0 ? 4 : 2;
     constexpr int CV = 16 / ELEM;
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
@@ -665,88 +759,65 @@ __device__ __forceinline__ bool tile_march(const DevReq& R, const Ray& ray, cons
     const int cap = R.box_bytes / ELEM;
     const bool act = ray.n > 0;
 
-    // ---- tile-wide set-up: common axis, slab range, lateral spread -------------
-    // reference ray (tile centre): position on plane z is cf + z * rf
-    float rf[3], cf[3];
-    {
-        const float ocm = ff_to_f(oc[M]), dcm = dc[M].hi;
-#pragma unroll
-        for (int a = 0; a < 3; ++a) {
-            rf[a] = a == M ? 1.0f : dc[a].hi / dcm;
-            cf[a] = a == M ? 0.0f : ff_to_f(oc[a]) - ocm * rf[a];
-        }
-    }
-    int zf = VR_BIG, zl = VR_BIG, dlo1 = VR_BIG, dhi1 = -VR_BIG, dlo2 = VR_BIG, dhi2 = -VR_BIG;
-    int sl1 = 0, sl2 = 0, okl = 1;
+    // ---- tile-wide range of sample planes along M -----------------------------
+    int zf = 0, zl = 0;
+    ff E[3];
     if (act) {
-        const ff t0 = sample_t(R, ray, 0), t1 = sample_t(R, ray, ray.n - 1);
-        float pf[3], pl[3];
+        const ff t1 = sample_t(R, ray, ray.n - 1);
+        const ff t0 = sample_t(R, ray, 0);
 #pragma unroll
-        for (int a = 0; a < 3; ++a) {
-            pf[a] = ff_to_f(ff_add(ray.o[a], ff_mul(t0, ray.d[a])));
-            pl[a] = ff_to_f(ff_add(ray.o[a], ff_mul(t1, ray.d[a])));
-        }
-        okl = (float)sgn * ray.d[M].hi >= 0.25f;
+        for (int a = 0; a < 3; ++a) E[a] = ff_add(ray.o[a], ff_mul(ray.tin, ray.d[a]));
+        const float pf = ff_to_f(ff_add(ray.o[M], ff_mul(t0, ray.d[M])));
+        const float pl = ff_to_f(ff_add(ray.o[M], ff_mul(t1, ray.d[M])));
         const float hm = (float)(N[M] - 1);
-        zf = (int)floorf(fminf(fmaxf(pf[M], 0.0f), hm));
-        zl = (int)floorf(fminf(fmaxf(pl[M], 0.0f), hm));
-        const float e1f = pf[A1] - __builtin_fmaf(pf[M], rf[A1], cf[A1]);
-        const float e1l = pl[A1] - __builtin_fmaf(pl[M], rf[A1], cf[A1]);
-        const float e2f = pf[A2] - __builtin_fmaf(pf[M], rf[A2], cf[A2]);
-        const float e2l = pl[A2] - __builtin_fmaf(pl[M], rf[A2], cf[A2]);
-        dlo1 = (int)floorf(fminf(e1f, e1l));
-        dhi1 = (int)ceilf(fmaxf(e1f, e1l));
-        dlo2 = (int)floorf(fminf(e2f, e2l));
-        dhi2 = (int)ceilf(fmaxf(e2f, e2l));
-        const float inv = 1.0f / fabsf(ray.d[M].hi);
-        sl1 = (int)ceilf(fabsf(ray.d[A1].hi) * inv * 1024.0f);
-        sl2 = (int)ceilf(fabsf(ray.d[A2].hi) * inv * 1024.0f);
+        zf = (int)floorf(fminf(fmaxf(pf, 0.0f), hm));
+        zl = (int)floorf(fminf(fmaxf(pl, 0.0f), hm));
+    } else {
+#pragma unroll
+        for (int a = 0; a < 3; ++a) E[a] = ff_make(0.0f);
     }
     {
-        const int zfn = wave_min(act ? zf : VR_BIG), zfx = wave_max(act ? zf : -VR_BIG);
-        const int zln = wave_min(act ? zl : VR_BIG), zlx = wave_max(act ? zl : -VR_BIG);
-        const int a = wave_min(dlo1), b = wave_max(dhi1), c = wave_min(dlo2), d = wave_max(dhi2);
-        const int e = wave_max(sl1), f = wave_max(sl2);
-        const bool okw = __ballot(!okl) == 0ull;
+        const int a = wave_min(act ? min(zf, zl) : VR_BIG);
+        const int b = wave_max(act ? max(zf, zl) : -VR_BIG);
         if (lane == 0) {
-            atomicMin(&sh.red[0], zfn);
-            atomicMax(&sh.red[1], zfx);
-            atomicMin(&sh.red[2], zln);
-            atomicMax(&sh.red[3], zlx);
-            atomicMin(&sh.red[4], a);
-            atomicMax(&sh.red[5], b);
-            atomicMin(&sh.red[6], c);
-            atomicMax(&sh.red[7], d);
-            atomicMax(&sh.red[8], e);
-            atomicMax(&sh.red[9], f);
-            if (!okw) atomicAnd(&sh.red[10], 0);
+            atomicMin(&sh.red[0], a);
+            atomicMax(&sh.red[1], b);
         }
     }
     __syncthreads();
-    if (!sh.red[10]) return false;
-    const bool any_ray = sh.red[0] != VR_BIG;
-    // slab thickness: the thickest whose worst-case box fits one buffer
-    int S = 0;
-    if (any_ray) {
-        const int sp1 = sh.red[5] - sh.red[4] + 1, sp2 = sh.red[7] - sh.red[6] + 1;
-        const float s1 = (float)sh.red[8] * (1.0f / 1024.0f), s2 = (float)sh.red[9] * (1.0f / 1024.0f);
-        for (int cand = 16; cand >= 1; cand >>= 1) {
-            int ext[3];
-            ext[M] = cand + 3;
-            ext[A1] = sp1 + (int)ceilf(cand * s1) + 4;
-            ext[A2] = sp2 + (int)ceilf(cand * s2) + 4;
-            const int vol = (ext[0] + 2 * CV) * ext[1] * ext[2];
-            if (vol <= cap) {
-                S = cand;
-                break;
-            }
-        }
-        if (S == 0) return false;
+    int zmin = sh.red[0], zmax = sh.red[1];
+    if (zmin == VR_BIG) {  // no ray of the tile meets the cube: no slab
+        zmin = 0;
+        zmax = -1;
     }
-    const int Z0 = sgn > 0 ? sh.red[0] : sh.red[1] + 1;
-    const int K = !any_ray ? 0 : (sgn > 0 ? (sh.red[3] - Z0) / S + 1 : (Z0 - 1 - sh.red[2]) / S + 1);
-    int k_last = 0;
-    if (act) k_last = min(max(sgn > 0 ? (zl - Z0) / S : (Z0 - 1 - zl) / S, 0), K - 1);
+    // planes: marching up, slabs start at zmin and go while the entry plane is
+    // <= zmax; marching down, they start at zmax + 1 and go while entry > zmin
+    auto slab_exists = [&](int ze) { return sgn > 0 ? ze <= zmax : ze > zmin; };
+    auto exit_plane = [&](const Slab& s) { return sgn > 0 ? s.z0 + s.S : s.z0; };
+    // wave 0 lays out the slabs (identical in every lane) and publishes them
+    // Buffers: a one-buffer box goes to the buffer the previous slab does not
+    // use; a two-buffer box, and any box after one, is copied late.
+    Slab w0 = {};
+    bool w0_first = true;
+    int w0_buf = 1;
+    auto produce = [&](int slot) {
+        Slab s = {};
+        if (w0_first) {
+            const int ze = sgn > 0 ? zmin : zmax + 1;
+            if (slab_exists(ze)) s = next_slab<M, CV, ELEM>(ze, sgn, VR_SMAX, cr, N, zmin, zmax);
+        } else if (w0.S != 0 && slab_exists(exit_plane(w0))) {
+            s = next_slab<M, CV, ELEM>(exit_plane(w0), sgn, w0.S, cr, N, zmin, zmax);
+        }
+        if (s.S != 0) {
+            const int buf = (s.big || w0.big) ? 0 : 1 - w0_buf;
+            s.boff = buf * R.box_bytes;
+            s.late = (!w0_first && (s.big || w0.big)) ? 1 : 0;
+            w0_buf = buf;
+        }
+        w0_first = false;
+        if (lane == 0) sh.ring[slot] = s;
+        w0 = s;
+    };
 
     // ---- per-ray state --------------------------------------------------------------
     const float om = act ? ff_to_f(ray.o[M]) : 0.0f;
@@ -756,68 +827,35 @@ __device__ __forceinline__ bool tile_march(const DevReq& R, const Ray& ray, cons
     Accum acc = {0.0f, 0.0f, 0.0f, 1.0f, -VR_INF};
     unsigned nexec = 0, nskip = 0;
     bool stopped = false;
-    // sample ranges: slab it holds [ks, ke0); slab it+1 [ke0, ke1); slab it+2 [ke1, ke2)
-    int ks = 0, ke0 = 0, ke1 = 0;
-    auto slab_end = [&](int k, int kprev) -> int {
-        if (!act || stopped) return kprev;
-        if (k >= k_last) return ray.n;
-        const SlabGeo<M> g = slab_geo<M>(k, Z0, S, sgn, rf, cf);
-        const float kf = ceilf(((g.zexit - om) * inv_dm - tinf) * inv_step - 0.5f);
+    // first sample past the exit plane of a slab
+    auto slab_end = [&](const Slab& s, int kprev) -> int {
+        if (!act || stopped || s.S == 0) return kprev;
+        const int zx = exit_plane(s);
+        if (sgn > 0 ? zx > zl : zx <= zl) return ray.n;
+        const float kf = ceilf((((float)zx - om) * inv_dm - tinf) * inv_step - 0.5f);
         return kf < (float)kprev ? kprev : (kf > (float)ray.n ? ray.n : (int)kf);
     };
-    // bounds of slab k for samples [k0, k1): reduce into descriptor k % VR_RING
-    auto slab_bounds = [&](int k, int k0, int k1) {
-        int mn[3] = {VR_BIG, VR_BIG, VR_BIG}, mx[3] = {-VR_BIG, -VR_BIG, -VR_BIG};
-        if (k1 > k0) {
-            const SlabGeo<M> g = slab_geo<M>(k, Z0, S, sgn, rf, cf);
-            float A[3], lo[3], hi[3], w[3];
-            slab_anchor(R, ray, k0, g.B0, A, lo, hi);
-            const int jl = k1 - 1 - k0;
-            const float jfl = (float)jl + ((k1 == ray.n && jl > 0) ? ray.last_adj : 0.0f);
-            const float p1[3] = {__builtin_fmaf(jfl, ray.dd[0], A[0]),
-                                 __builtin_fmaf(jfl, ray.dd[1], A[1]),
-                                 __builtin_fmaf(jfl, ray.dd[2], A[2])};
-            int i0[3], i1[3];
-            floor_idx<INTERP>(A, lo, hi, i0, w);
-            floor_idx<INTERP>(p1, lo, hi, i1, w);
-#pragma unroll
-            for (int a = 0; a < 3; ++a) {
-                mn[a] = min(i0[a], i1[a]);
-                mx[a] = max(i0[a], i1[a]);
-            }
-        }
-#pragma unroll
-        for (int a = 0; a < 3; ++a) {
-            mn[a] = wave_min(mn[a]);
-            mx[a] = wave_max(mx[a]);
-        }
-        if (lane == 0 && mn[0] != VR_BIG) {
-            SlabDesc& d = sh.d[k % VR_RING];
-#pragma unroll
-            for (int a = 0; a < 3; ++a) {
-                atomicMin(&d.bmin[a], mn[a]);
-                atomicMax(&d.bmax[a], mx[a]);
-            }
-        }
-    };
-    // skip-grid words of slab k's cells: issue the loads (one cell row per thread)
+    // skip-grid words of a slab's cells: issue the loads (one cell row per thread)
     const int Cx = 4 * R.cube.bx, Cy = 4 * R.cube.by;
-    auto bits_issue = [&](int k, uint32_t& w0, uint32_t& w1, uint32_t& mask0, uint32_t& mask1,
+    auto bits_issue = [&](const Slab& s, uint32_t& w0w, uint32_t& w1w, uint32_t& m0, uint32_t& m1,
                           bool& wide) {
-        w0 = w1 = mask0 = mask1 = 0u;
+        w0w = w1w = m0 = m1 = 0u;
         wide = false;
-        const SlabGeo<M> g = slab_geo<M>(k, Z0, S, sgn, rf, cf);
-        const SlabDesc& d = sh.d[k % VR_RING];
-        if (d.bmin[0] > d.bmax[0]) return;
+        if (s.S == 0 || s.elems == 0) return;
         int c0[3], c1[3];
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
-            c0[a] = min(max(g.B0[a] + d.bmin[a], 0), N[a] - 1) >> 3;
-            c1[a] = min(max(g.B0[a] + d.bmax[a], 0), N[a] - 1) >> 3;
+            c0[a] = s.lo[a] >> 3;
+            c1[a] = (s.lo[a] + s.dim[a] - 2) >> 3;
         }
         const int ny_ = c1[1] - c0[1] + 1, nrow = ny_ * (c1[2] - c0[2] + 1);
+        if (nrow > VR_WG) {
+            wide = tid == 0;  // more cell rows than threads: treated as active
+            return;
+        }
         if (tid >= nrow) return;
-        const int cy = c0[1] + tid % ny_, cz = c0[2] + tid / ny_;
+        const int czr = div_small(tid, ny_, 1.0f / (float)ny_);
+        const int cy = c0[1] + tid - czr * ny_, cz = c0[2] + czr;
         const int64_t b0 = ((int64_t)cz * Cy + cy) * Cx + c0[0];
         const int64_t b1 = b0 + (c1[0] - c0[0]);
         const int64_t wa = b0 >> 5, wb = b1 >> 5;
@@ -827,126 +865,121 @@ __device__ __forceinline__ bool tile_march(const DevReq& R, const Ray& ray, cons
         }
         const uint32_t lo_bit = (uint32_t)(b0 & 31), hi_bit = (uint32_t)(b1 & 31);
         if (wa == wb) {
-            mask0 = (hi_bit == 31 ? 0xffffffffu : ((1u << (hi_bit + 1)) - 1u)) & ~((1u << lo_bit) - 1u);
+            m0 = (hi_bit == 31 ? 0xffffffffu : ((1u << (hi_bit + 1)) - 1u)) & ~((1u << lo_bit) - 1u);
         } else {
-            mask0 = ~((1u << lo_bit) - 1u);
-            mask1 = hi_bit == 31 ? 0xffffffffu : ((1u << (hi_bit + 1)) - 1u);
-            w1 = R.cube.cellbits[wb];
+            m0 = ~((1u << lo_bit) - 1u);
+            m1 = hi_bit == 31 ? 0xffffffffu : ((1u << (hi_bit + 1)) - 1u);
+            w1w = R.cube.cellbits[wb];
         }
-        w0 = R.cube.cellbits[wa];
+        w0w = R.cube.cellbits[wa];
     };
-    // box DMA of slab k into buffer k & 1
-    auto box_dma = [&](int k) {
-        const SlabGeo<M> g = slab_geo<M>(k, Z0, S, sgn, rf, cf);
-        const SlabDesc& d = sh.d[k % VR_RING];
-        const BoxGeo b = box_geo<DT, INTERP>(d, g.B0);
-        if (b.empty || !d.any || b.elems > cap) return;
-        uint8_t* buf = boxes + (k & 1) * R.box_bytes;
-        const int total = b.nc * b.bdim[1] * b.bdim[2];
-        const float inv_nc = 1.0f / (float)b.nc, inv_b1 = 1.0f / (float)b.bdim[1];
+    // copy a slab's box into buffer `which`: LDS slot q (row-major over
+    // [z][y][x-chunk], np slots per row) receives 16 bytes at byte 16 q; each
+    // thread walks its slots q = tid + 512 k with incremental (chunk, row) indices
+    const uint32_t bstride = (uint32_t)R.cube.stride;
+    auto staged = [&](const Slab& s) { return s.elems <= (s.big ? 2 * cap : cap); };
+    auto box_dma = [&](const Slab& s) {
+        if (s.S == 0 || s.elems == 0 || !staged(s)) return;
+        uint8_t* buf = boxes + s.boff;
+        const int nc = s.np, d1 = s.dim[1], ncd = s.nc;
+        const int total = nc * d1 * s.dim[2];
+        const float inv_nc = 1.0f / (float)nc, inv_d1 = 1.0f / (float)d1;
+        const int row = div_small(tid, nc, inv_nc);
+        int c = tid - row * nc;
+        int iz = div_small(row, d1, inv_d1);
+        int iy = row - iz * d1;
+        const int qr = div_small(VR_WG, nc, inv_nc), qc = VR_WG - qr * nc;
+        const int dz = div_small(qr, d1, inv_d1), dy = qr - dz * d1;
         for (int q0 = wave * 64; q0 < total; q0 += VR_WG) {
-            const int q = q0 + lane;
-            if (q < total) {
-                const int rowi = div_small(q, b.nc, inv_nc);
-                const int c = q - rowi * b.nc;
-                const int iz = div_small(rowi, b.bdim[1], inv_b1);
-                const int iy = rowi - iz * b.bdim[1];
-                const int gy = min(b.g0[1] + iy, N[1] - 1), gz = min(b.g0[2] + iz, N[2] - 1);
-                const int x = b.xa + c * CV;
+            if (q0 + lane < total) {
+                const int gy = min(s.lo[1] + iy, N[1] - 1), gz = min(s.lo[2] + iz, N[2] - 1);
+                const int x = s.xa + min(c, ncd - 1) * CV;  // the pad slot repeats the last chunk
                 const int bxb = min(x >> 5, R.cube.bx - 1);
                 const int lx = x - 32 * bxb;
-                const uint64_t slot = ((uint64_t)(gz >> 5) * R.cube.by + (gy >> 5)) * R.cube.bx + bxb;
-                const uint8_t* src = R.cube.pool + slot * R.cube.stride +
-                                     (uint64_t)(((gz & 31) * VR_BRICK_APRON + (gy & 31)) * R.cube.row + lx) * ELEM;
+                const uint32_t slot = ((uint32_t)(gz >> 5) * (uint32_t)R.cube.by + (uint32_t)(gy >> 5)) *
+                                          (uint32_t)R.cube.bx + (uint32_t)bxb;
+                const uint32_t off = (uint32_t)((((gz & 31) * VR_BRICK_APRON + (gy & 31)) * R.cube.row + lx) * ELEM);
+                const uint8_t* src = R.cube.pool + ((uint64_t)slot * bstride + off);
                 __builtin_amdgcn_global_load_lds((const void*)src,
                                                  (__attribute__((address_space(3))) void*)(buf + q0 * 16),
                                                  16, 0, 0);
+            }
+            c += qc;
+            const int carry = c >= nc ? 1 : 0;
+            c -= carry * nc;
+            iy += dy + carry;
+            iz += dz;
+            if (iy >= d1) {
+                iy -= d1;
+                ++iz;
             }
         }
     };
 
     // ---- prologue: slabs 0 and 1 ------------------------------------------------------
-    if (K > 0) {
-        ke0 = slab_end(0, 0);
-        slab_bounds(0, 0, ke0);
-        if (K > 1) {
-            ke1 = slab_end(1, ke0);
-            slab_bounds(1, ke0, ke1);
-        }
+    if (wave == 0) {
+        produce(0);
+        produce(1);
     }
     __syncthreads();
+    Slab s0 = sh.ring[0], s1 = sh.ring[1];
+    int ks = 0, ke0 = slab_end(s0, 0);
     if (R.use_skip) {
-        for (int k = 0; k < min(K, 2); ++k) {
-            uint32_t w0, w1, m0, m1;
-            bool wide;
-            bits_issue(k, w0, w1, m0, m1, wide);
-            if (wide || (w0 & m0) || (w1 & m1)) sh.d[k % VR_RING].any = 1;
-        }
+        uint32_t w0w, w1w, m0, m1;
+        bool wide;
+        bits_issue(s0, w0w, w1w, m0, m1, wide);
+        if (wide || (w0w & m0) || (w1w & m1)) sh.any[0] = 1;
+        bits_issue(s1, w0w, w1w, m0, m1, wide);
+        if (wide || (w0w & m0) || (w1w & m1)) sh.any[1] = 1;
         __syncthreads();
     }
-    if (K > 0) box_dma(0);
+    if (sh.any[0]) box_dma(s0);
 
     // ---- slab pipeline -----------------------------------------------------------------
-    for (int it = 0; it < K; ++it) {
-        int ke2 = ke1;
-        if (it + 2 < K) {
-            ke2 = slab_end(it + 2, ke1);
-            slab_bounds(it + 2, ke1, ke2);
-        }
+    for (int it = 0; s0.S != 0; ++it) {
+        if (wave == 0) produce((it + 2) & 3);
         if (tid == 0) {
-            if (it + 3 < K) {
-                SlabDesc& d = sh.d[(it + 3) % VR_RING];
-#pragma unroll
-                for (int a = 0; a < 3; ++a) {
-                    d.bmin[a] = VR_BIG;
-                    d.bmax[a] = -VR_BIG;
-                }
-                d.any = R.use_skip ? 0 : 1;
-            }
+            sh.any[(it + 3) & 7] = R.use_skip ? 0 : 1;
             sh.alive[it % 3] = 0;
         }
         __builtin_amdgcn_s_waitcnt(0);  // own box copies of slab it have landed
         __syncthreads();
         if (it > 0 && sh.alive[(it - 1) % 3] == 0) break;
+        const Slab s2 = sh.ring[(it + 2) & 3];
         uint32_t bw0 = 0, bw1 = 0, bm0 = 0, bm1 = 0;
         bool bwide = false;
-        if (R.use_skip && it + 2 < K) bits_issue(it + 2, bw0, bw1, bm0, bm1, bwide);
-        if (it + 1 < K) box_dma(it + 1);
+        if (R.use_skip) bits_issue(s2, bw0, bw1, bm0, bm1, bwide);
+        if (!s1.late && sh.any[(it + 1) & 7]) box_dma(s1);
+        const int ke1 = slab_end(s1, ke0);
         // ---- sample slab it
-        {
-            const SlabGeo<M> g = slab_geo<M>(it, Z0, S, sgn, rf, cf);
-            const SlabDesc& d = sh.d[it % VR_RING];
-            const BoxGeo b = box_geo<DT, INTERP>(d, g.B0);
-            const int cnt_s = ke0 - ks;
-            if (cnt_s > 0 && !stopped) {
-                if (!d.any) {
-                    nskip += (unsigned)cnt_s;
-                } else {
-                    const bool staged = b.elems <= cap;
-                    const VT* box = (const VT*)(boxes + (it & 1) * R.box_bytes);
-                    const int sy = b.pitch, sz = b.pitch * b.bdim[1];
-                    const int xoff = g.B0[0] - b.xa;
-                    float A[3], lo[3], hi[3];
-                    slab_anchor(R, ray, ks, g.B0, A, lo, hi);
+        const int cnt_s = ke0 - ks;
+        if (cnt_s > 0 && !stopped) {
+            if (!sh.any[it & 7]) {
+                nskip += (unsigned)cnt_s;
+            } else {
+                float A[3], cl[3], ch[3];
+                {
+                    const float kf = (float)ks + 0.5f;
+                    ff sk = two_prod(kf, R.step.hi);
+                    sk.lo = __builtin_fmaf(kf, R.step.lo, sk.lo);
+#pragma unroll
+                    for (int a = 0; a < 3; ++a) {
+                        A[a] = anchor_axis(E[a], ray.d[a], sk, s0.lo[a]);
+                        cl[a] = (float)(-s0.lo[a]);
+                        ch[a] = (float)(N[a] - 1 - s0.lo[a]);
+                    }
+                }
+                auto run = [&](auto fetch) {
                     for (int j = 0; j < cnt_s; ++j) {
                         const bool last = (ks + j == ray.n - 1);
-                        const float jf = (float)j + ((last && j > 0) ? ray.last_adj : 0.0f);
+                        const float jf = (float)j + (last ? ray.last_adj : 0.0f);
                         const float p[3] = {__builtin_fmaf(jf, ray.dd[0], A[0]),
                                             __builtin_fmaf(jf, ray.dd[1], A[1]),
                                             __builtin_fmaf(jf, ray.dd[2], A[2])};
                         int i[3];
                         float w[3];
-                        floor_idx<INTERP>(p, lo, hi, i, w);
-                        float v;
-                        if (staged) {
-                            const int idx = ((i[2] - b.blo[2]) * b.bdim[1] + (i[1] - b.blo[1])) * b.pitch +
-                                            (i[0] + xoff);
-                            v = interp_at<DT, INTERP>(box + idx, sy, sz, w[0], w[1], w[2]);
-                        } else {
-                            v = interp_at<DT, INTERP>(
-                                pool_ptr<DT>(R.cube, g.B0[0] + i[0], g.B0[1] + i[1], g.B0[2] + i[2]),
-                                R.cube.row, VR_BRICK_APRON * R.cube.row, w[0], w[1], w[2]);
-                        }
+                        floor_idx<INTERP>(p, cl, ch, i, w);
+                        const float v = fetch(i, w);
                         ++nexec;
                         if (MODE == 1) {
                             acc.m = fmaxf(acc.m, v);
@@ -955,16 +988,36 @@ __device__ __forceinline__ bool tile_march(const DevReq& R, const Ray& ray, cons
                             break;
                         }
                     }
+                };
+                if (staged(s0)) {
+                    const LVT* box = (const LVT*)(boxes + s0.boff);
+                    const int pitch = s0.np * CV;
+                    const int sy = pitch, sz = pitch * s0.dim[1];
+                    const int xoff = s0.lo[0] - s0.xa;
+                    run([&](const int* i, const float* w) {
+                        return interp_box<DT, INTERP>(box, (i[2] * s0.dim[1] + i[1]) * pitch + (i[0] + xoff),
+                                                      sy, sz, w[0], w[1], w[2]);
+                    });
+                } else {
+                    run([&](const int* i, const float* w) {
+                        return interp_at<DT, INTERP>(
+                            pool_ptr<DT>(R.cube, s0.lo[0] + i[0], s0.lo[1] + i[1], s0.lo[2] + i[2]),
+                            R.cube.row, VR_BRICK_APRON * R.cube.row, w[0], w[1], w[2]);
+                    });
                 }
             }
         }
-        if (R.use_skip && it + 2 < K && (bwide || (bw0 & bm0) || (bw1 & bm1)))
-            sh.d[(it + 2) % VR_RING].any = 1;
+        if (R.use_skip && (bwide || (bw0 & bm0) || (bw1 & bm1))) sh.any[(it + 2) & 7] = 1;
         const bool done = !act || stopped || ke0 >= ray.n;
         if (__ballot(!done) != 0ull && lane == 0) sh.alive[it % 3] = 1;
+        if (s1.late) {  // the box of slab it + 1 needs the LDS slab it used
+            __syncthreads();
+            if (sh.any[(it + 1) & 7]) box_dma(s1);
+        }
         ks = ke0;
         ke0 = ke1;
-        ke1 = ke2;
+        s0 = s1;
+        s1 = s2;
     }
     __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
@@ -979,9 +1032,8 @@ __device__ __forceinline__ bool tile_march(const DevReq& R, const Ray& ray, cons
     return true;
 }
 
-// Returns false (having rendered nothing) when the tile's rays do not share a
-// direction along one axis, or no slab box fits; the caller then runs the
-// per-ray walker.
+// Returns false (having rendered nothing) when the rays of the tile do not all
+// advance along one axis; the caller then runs the per-ray walker.
 template <int MODE, int DT, int INTERP>
 __device__ __forceinline__ bool render_tile(const DevReq& R, const int tx, const int ty,
                                             const float* __restrict__ tfl,
@@ -994,40 +1046,47 @@ __device__ __forceinline__ bool render_tile(const DevReq& R, const int tx, const
     if (tid == 0) {
         sh.red[0] = VR_BIG;
         sh.red[1] = -VR_BIG;
-        sh.red[2] = VR_BIG;
-        sh.red[3] = -VR_BIG;
-        sh.red[4] = VR_BIG;
-        sh.red[5] = -VR_BIG;
-        sh.red[6] = VR_BIG;
-        sh.red[7] = -VR_BIG;
-        sh.red[8] = 0;
-        sh.red[9] = 0;
-        sh.red[10] = 1;
-        for (int q = 0; q < VR_RING; ++q) {
-            for (int a = 0; a < 3; ++a) {
-                sh.d[q].bmin[a] = VR_BIG;
-                sh.d[q].bmax[a] = -VR_BIG;
-            }
-            sh.d[q].any = R.use_skip ? 0 : 1;
-        }
+        for (int q = 0; q < 8; ++q) sh.any[q] = R.use_skip ? 0 : 1;
         sh.alive[0] = sh.alive[1] = sh.alive[2] = 0;
     }
-    Ray ray;
-    ray.n = 0;
-    if (inimg) ray_setup(R, px, py, ray);
-    // tile reference ray (identical in every lane) fixes the major axis and slab origins
+    // tile centre ray fixes the major axis; the corner rays bound the tile's rays
     ff oc[3], dc[3];
     ray_dir(R.cam, (float)(tx * VR_TW) + 0.5f * VR_TW, (float)(ty * VR_TH) + 0.5f * VR_TH, oc, dc);
     const float ad0 = fabsf(dc[0].hi), ad1 = fabsf(dc[1].hi), ad2 = fabsf(dc[2].hi);
     const int m = (ad2 > ad0 && ad2 > ad1) ? 2 : (ad1 > ad0 ? 1 : 0);
     const float dm = m == 0 ? dc[0].hi : (m == 1 ? dc[1].hi : dc[2].hi);
     const int sgn = dm > 0.0f ? 1 : -1;
+    const int m1 = m == 2 ? 0 : m + 1, m2 = m == 0 ? 2 : m - 1;
+    Corners cr;
+    bool ok = true;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const float fi = (k & 1) ? (float)min(tx * VR_TW + VR_TW, R.W) - 0.5f : (float)(tx * VR_TW) + 0.5f;
+        const float fj = (k & 2) ? (float)min(ty * VR_TH + VR_TH, R.H) - 0.5f : (float)(ty * VR_TH) + 0.5f;
+        ff o[3], d[3];
+        ray_dir(R.cam, fi, fj, o, d);
+        const float o3[3] = {ff_to_f(o[0]), ff_to_f(o[1]), ff_to_f(o[2])};
+        const float d3[3] = {d[0].hi, d[1].hi, d[2].hi};
+        const float dmk = m == 0 ? d3[0] : (m == 1 ? d3[1] : d3[2]);
+        const float omk = m == 0 ? o3[0] : (m == 1 ? o3[1] : o3[2]);
+        ok = ok && (float)sgn * dmk >= 0.25f;
+        const float r1 = (m1 == 0 ? d3[0] : (m1 == 1 ? d3[1] : d3[2])) / dmk;
+        const float r2 = (m2 == 0 ? d3[0] : (m2 == 1 ? d3[1] : d3[2])) / dmk;
+        cr.r[k][0] = r1;
+        cr.r[k][1] = r2;
+        cr.c[k][0] = (m1 == 0 ? o3[0] : (m1 == 1 ? o3[1] : o3[2])) - omk * r1;
+        cr.c[k][1] = (m2 == 0 ? o3[0] : (m2 == 1 ? o3[1] : o3[2])) - omk * r2;
+    }
+    if (!ok) return false;
+    Ray ray;
+    ray.n = 0;
+    if (inimg) ray_setup(R, px, py, ray);
     __syncthreads();
     if (m == 0)
-        return tile_march<MODE, DT, INTERP, 0>(R, ray, px, py, inimg, oc, dc, sgn, tfl, boxes, sh, cnt);
+        return tile_march<MODE, DT, INTERP, 0>(R, ray, px, py, inimg, cr, sgn, tfl, boxes, sh, cnt);
     if (m == 1)
-        return tile_march<MODE, DT, INTERP, 1>(R, ray, px, py, inimg, oc, dc, sgn, tfl, boxes, sh, cnt);
-    return tile_march<MODE, DT, INTERP, 2>(R, ray, px, py, inimg, oc, dc, sgn, tfl, boxes, sh, cnt);
+        return tile_march<MODE, DT, INTERP, 1>(R, ray, px, py, inimg, cr, sgn, tfl, boxes, sh, cnt);
+    return tile_march<MODE, DT, INTERP, 2>(R, ray, px, py, inimg, cr, sgn, tfl, boxes, sh, cnt);
 }
 
 // One tile: slab-staged if possible, else one independent walker per ray.

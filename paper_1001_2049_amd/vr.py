@@ -8,7 +8,9 @@ built, ``lib()`` raises.
 """
 from __future__ import annotations
 
+import atexit
 import ctypes
+import weakref
 import math
 import os
 import re
@@ -196,8 +198,10 @@ def torch_allocator(device: int):
         except Exception:  # noqa: BLE001 - reported to the library as NULL
             return None
 
+    delete = torch.cuda.caching_allocator_delete
+
     def _free(ptr, nbytes, user):
-        torch.cuda.caching_allocator_delete(ptr)
+        delete(ptr)
 
     a = vr_allocator()
     a.alloc = vr_allocator._fields_[0][1](_alloc)
@@ -205,6 +209,20 @@ def torch_allocator(device: int):
     a.user = None
     a._keep = (_alloc, _free, a.alloc, a.free)
     return a
+
+
+# contexts still open at interpreter exit are destroyed while PyTorch (which
+# owns their device memory) is still intact
+_LIVE = weakref.WeakSet()
+
+
+@atexit.register
+def _close_all():
+    for r in list(_LIVE):
+        try:
+            r.close()
+        except Exception:  # noqa: BLE001
+            pass
 
 
 class Renderer:
@@ -219,6 +237,7 @@ class Renderer:
         check(lib().vr_create(device, budget_bytes,
                               ctypes.byref(self._alloc) if self._alloc else None, ctypes.byref(h)))
         self.ctx = h
+        _LIVE.add(self)
 
     def close(self):
         if self.ctx:

@@ -21,3 +21,11 @@ def _c_libraries():
     synth.lib()
     oracle.lib()
     yield
+
+
+@pytest.fixture(scope="session")
+def full_workload():
+    """The full-size workload (512x512x1024 float32 cube, generated once per session)."""
+    import synth
+    wl = synth.full()
+    return wl, synth.cube(wl.cube), synth.ramp_tf(256, wl.kappa_max)

@@ -199,9 +199,14 @@ def test_camera_inside_cube_and_missing_view(R, tiny, tiny_cube):
 @pytest.mark.parametrize("mode,interp", [("ea", "trilinear"), ("mip", "trilinear"),
                                          ("ea", "nearest"), ("mip", "nearest")])
 def test_skip_is_bit_invisible(R, tiny, tiny_cube, mode, interp):
+    """With the transfer function starting at a 5.5 sigma clip, noise alone
+    rarely reaches the clip, most cells are empty and skipping removes work;
+    the images with and without it are bit-identical."""
     wl, vol, tf = tiny
     cam = synth.orbit_camera(64, 64, 128, 0.7, 0.2)
-    set_state(R, wl, tf, cam)
+    R.set_transfer_function(tf, 5.5, wl.v1)
+    R.set_noise_clip(5.5, 1.0)
+    R.set_camera(cam)
     a, sa = R.render(tiny_cube, 192, 160, mode=mode, interp=interp, use_skip=True, stats=True)
     b, sb = R.render(tiny_cube, 192, 160, mode=mode, interp=interp, use_skip=False, stats=True)
     c = R.render(tiny_cube, 192, 160, mode=mode, interp=interp, use_skip=True)
@@ -242,3 +247,33 @@ def test_stats_count_nominal_samples(R, tiny, tiny_cube):
     assert st["samples_nominal"] == int(ref["n_nominal"].sum())
     assert st["rays_hit"] == int(((ref["flags"] & oracle.FLAG_HIT) > 0).sum())
     assert st["kernel_ms"] > 0
+
+
+# ---------------------------------------------------------------------------
+# full-size workload in the benchmark's launch configuration, sampled pixels
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("mode", ["ea", "mip"])
+def test_full_cube_sampled_pixels(R, full_workload, mode):
+    """512x512x1024 float32 cube, 1024^2 perspective orbit views, skipping on,
+    early termination at 0.99: the whole image is rendered as in the benchmark
+    and 2000 seeded pixels per view are compared with the reference."""
+    wl, vol, tf = full_workload
+    cube = R.upload(vol, "f32")
+    try:
+        kw = wl_kwargs(wl, tf)
+        for vi, (th, ph) in enumerate(synth.orbit_angles(wl.extra["camera_seed"], 3)):
+            cam = synth.orbit_camera(512, 512, 1024, th, ph)
+            set_state(R, wl, tf, cam)
+            img, st = R.render(cube, 1024, 1024, mode=mode, stats=True)
+            got_img = to_np(img)
+            px = synth.pixel_subset(500 + vi, 1024, 1024, 2000)
+            got = got_img[px[:, 1], px[:, 0]]
+            ref = ref_render(vol, kw, cam, 1024, 1024, mode, "trilinear", pixels=px)
+            if mode == "ea":
+                info = compare_ea(got, ref["values"], TOL_F32, ref["flags"])
+            else:
+                info = compare_mip(got, ref["values"], TOL_F32, ref["flags"])
+            print("full f32 view%d %s %s stats=%s" % (vi, mode, info, st))
+            assert st["samples_exec"] <= st["samples_nominal"]
+    finally:
+        R.release(cube)
