@@ -375,6 +375,35 @@ static vr_status ensure_counters(Ctx* c, int count) {
     return VR_OK;
 }
 
+// Dispatch-order scratch of a single render; a render on another stream waits
+// for the last one that read it.
+static vr_status ensure_order(Ctx* c, int ntiles, hipStream_t s) {
+    vr_status st = VR_OK;
+    if (c->order_cap < ntiles) {
+        if (c->order.ptr) {
+            st = hip_check(hipDeviceSynchronize(), "hipDeviceSynchronize");
+            if (st != VR_OK) return st;
+            dev_free(c, c->order, false);
+        }
+        c->order_cap = 0;
+        const int cap = std::max(ntiles, 4096);
+        st = dev_alloc(c, c->order, (uint64_t)cap * sizeof(int), false);
+        if (st != VR_OK) return st;
+        c->order_cap = cap;
+    }
+    if (!c->ohist.ptr) {
+        st = dev_alloc(c, c->ohist, 1024, false);
+        if (st != VR_OK) return st;
+    }
+    if (!c->order_done) {
+        st = hip_check(hipEventCreateWithFlags(&c->order_done, hipEventDisableTiming), "hipEventCreate");
+        if (st != VR_OK) return st;
+    } else {
+        st = hip_check(hipStreamWaitEvent(s, c->order_done, 0), "hipStreamWaitEvent");
+    }
+    return st;
+}
+
 static void fill_stats(const DevCounters& d, float ms, vr_stats* st) {
     st->samples_nominal = d.samples_nominal;
     st->samples_exec = d.samples_exec;
@@ -427,6 +456,8 @@ void free_batch_bufs(Ctx* c, BatchBufs& bb) {
     dev_free(c, bb.items, false);
     dev_free(c, bb.head, false);
     dev_free(c, bb.hdr, false);
+    dev_free(c, bb.sorted, false);
+    dev_free(c, bb.hist, false);
     if (bb.pin_reqs) (void)hipHostFree(bb.pin_reqs);
     if (bb.pin_items) (void)hipHostFree(bb.pin_items);
     if (bb.pin_hdr) (void)hipHostFree(bb.pin_hdr);
@@ -453,6 +484,7 @@ static vr_status grow_batch(Ctx* c, BatchBufs& bb, int nreq, int nitems) {
     if (!bb.head.ptr) {
         st = dev_alloc(c, bb.head, 256, false);
         if (st == VR_OK) st = dev_alloc(c, bb.hdr, 256, false);
+        if (st == VR_OK) st = dev_alloc(c, bb.hist, 1024, false);
         if (st == VR_OK)
             st = hip_check(hipHostMalloc((void**)&bb.pin_hdr, 256, 0), "hipHostMalloc");
         if (st != VR_OK) return st;
@@ -475,10 +507,12 @@ static vr_status grow_batch(Ctx* c, BatchBufs& bb, int nreq, int nitems) {
     if (bb.items_cap < nitems) {
         const int cap = pow2_at_least(nitems, 4096);
         dev_free(c, bb.items, false);
+        dev_free(c, bb.sorted, false);
         if (bb.pin_items) (void)hipHostFree(bb.pin_items);
         bb.pin_items = nullptr;
         bb.items_cap = 0;
         st = dev_alloc(c, bb.items, (uint64_t)cap * sizeof(DevItem), false);
+        if (st == VR_OK) st = dev_alloc(c, bb.sorted, (uint64_t)cap * sizeof(DevItem), false);
         if (st != VR_OK) return st;
         st = hip_check(hipHostMalloc((void**)&bb.pin_items, (size_t)cap * sizeof(DevItem), 0),
                        "hipHostMalloc");
@@ -511,8 +545,9 @@ static vr_status enqueue_batch(Ctx* c, BatchBufs& bb, int count, int nitems, siz
                            "hipMemcpyAsync");
         if (st == VR_OK)
             st = hip_check(vr_launch_batch((const DevReq*)bb.reqs.ptr, (const DevItem*)bb.items.ptr,
-                                           (const int*)bb.hdr.ptr, (unsigned*)bb.head.ptr,
-                                           dev_counters, lds, grid, s),
+                                           (const int*)bb.hdr.ptr, use_graph ? bb.items_cap : nitems,
+                                           (DevItem*)bb.sorted.ptr, (unsigned*)bb.hist.ptr,
+                                           (unsigned*)bb.head.ptr, dev_counters, lds, grid, s),
                            "batch launch");
         return st;
     };
@@ -740,6 +775,9 @@ vr_status vr_destroy(vr_ctx ctx) {
             for (auto& kv : c->tfs) ts.push_back(kv.second.get());
             for (Tf* t : ts) release_tf(c, t);
             dev_free(c, c->counters, false);
+            dev_free(c, c->order, false);
+            dev_free(c, c->ohist, false);
+            if (c->order_done) (void)hipEventDestroy(c->order_done);
             free_batch_bufs(c, c->batch);
         }
     });
@@ -1047,7 +1085,11 @@ vr_status vr_render(vr_ctx ctx, vr_cube cube, const vr_render_params* params, vo
             if (st == VR_OK) st = hip_check(hipEventRecord(e0, s), "hipEventRecord");
             if (st != VR_OK) return st;
         }
-        st = hip_check(vr_launch_render(R, dc, s), "render launch");
+        st = ensure_order(c, R.tiles_x * R.tiles_y, s);
+        if (st != VR_OK) return st;
+        st = hip_check(vr_launch_render(R, (int*)c->order.ptr, (unsigned*)c->ohist.ptr, dc, s),
+                       "render launch");
+        if (st == VR_OK) st = hip_check(hipEventRecord(c->order_done, s), "hipEventRecord");
         if (st != VR_OK) return st;
         st = mark_use(c, cu, tf, me, s);
         if (st != VR_OK) return st;

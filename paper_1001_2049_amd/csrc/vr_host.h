@@ -76,6 +76,7 @@ struct Server;
 // graphs captured over those buffers (one per shape class).
 struct BatchBufs {
     DevBuf reqs, items, head, hdr;
+    DevBuf sorted, hist;  // work list reordered most expensive first; bucket counts
     DevReq* pin_reqs = nullptr;
     DevItem* pin_items = nullptr;
     int* pin_hdr = nullptr;
@@ -108,6 +109,9 @@ struct Ctx {
     // scratch for single renders / batches
     DevBuf counters;             // DevCounters x capacity
     int counters_cap = 0;
+    DevBuf order, ohist;         // single-render dispatch order and its bucket counts
+    int order_cap = 0;
+    hipEvent_t order_done = nullptr;  // last render that read `order`
     BatchBufs batch;
 
     Server* server = nullptr;

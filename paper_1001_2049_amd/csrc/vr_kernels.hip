@@ -216,13 +216,6 @@ __global__ __launch_bounds__(VR_BB_WG) void k_cellbits(const uint64_t* __restric
 // ---------------------------------------------------------------------------
 // Rendering: shared pieces
 // ---------------------------------------------------------------------------
-// Workgroups are dealt to the 8 XCDs round-robin; remap so that each XCD gets
-// a contiguous band of tiles (neighbouring rays then share that XCD's L2).
-__device__ __forceinline__ int xcd_swizzle(int g, int num) {
-    const int x = g & 7, k = g >> 3, per = num >> 3, rem = num & 7;
-    return (x < rem ? x * (per + 1) : rem * (per + 1) + (x - rem) * per) + k;
-}
-
 struct LaneCounts {
     unsigned nominal, exec, hit, ert, skipped;
 };
@@ -1120,7 +1113,8 @@ __device__ __forceinline__ void flush_counts(const LaneCounts& c, DevCounters* c
 
 // dynamic LDS: transfer-function rows (n x 32 bytes), then two slab boxes
 template <int MODE, int DT, int INTERP>
-__global__ __launch_bounds__(VR_WG) void k_render(const DevReq R, DevCounters* cnt) {
+__global__ __launch_bounds__(VR_WG) void k_render(const DevReq R, const int* __restrict__ order,
+                                                   DevCounters* cnt) {
     extern __shared__ float4 lds4[];
     __shared__ unsigned wgc[5];
     __shared__ TileShared sh;
@@ -1132,11 +1126,105 @@ __global__ __launch_bounds__(VR_WG) void k_render(const DevReq R, DevCounters* c
     }
     if (cnt && threadIdx.x < 5) wgc[threadIdx.x] = 0u;
     __syncthreads();
-    const int tile = xcd_swizzle(blockIdx.x, gridDim.x);
+    const int tile = order[blockIdx.x];
     const int tx = tile % R.tiles_x, ty = tile / R.tiles_x;
     LaneCounts c = {0u, 0u, 0u, 0u, 0u};
     render_tile_any<MODE, DT, INTERP>(R, tx, ty, tfl, (uint8_t*)lds4 + tf_bytes, sh, c);
     if (cnt) flush_counts(c, cnt, wgc);
+}
+
+// ---------------------------------------------------------------------------
+// Dispatch order: tiles are handed out most expensive first, so that the
+// launch does not end waiting on a few long tiles (longest-processing-time
+// scheduling).  The cost estimate is the longest lattice among a tile's four
+// corner rays and its centre ray; a counting sort over 128 logarithmic cost
+// buckets orders the work (the order inside a bucket is arbitrary, and no
+// order changes any pixel).
+// ---------------------------------------------------------------------------
+#define VR_NBUCKET 128
+
+__device__ __forceinline__ int tile_bucket(const DevReq& R, int tile) {
+    const int tx = tile % R.tiles_x, ty = tile / R.tiles_x;
+    const float xa = (float)(tx * VR_TW) + 0.5f, xb = (float)min(tx * VR_TW + VR_TW, R.W) - 0.5f;
+    const float ya = (float)(ty * VR_TH) + 0.5f, yb = (float)min(ty * VR_TH + VR_TH, R.H) - 0.5f;
+    const float N[3] = {(float)R.cube.nx, (float)R.cube.ny, (float)R.cube.nz};
+    float best = 0.0f;
+    for (int k = 0; k < 5; ++k) {
+        const float fi = k == 4 ? 0.5f * (xa + xb) : ((k & 1) ? xb : xa);
+        const float fj = k == 4 ? 0.5f * (ya + yb) : ((k & 2) ? yb : ya);
+        ff o[3], d[3];
+        ray_dir(R.cam, fi, fj, o, d);
+        float t0 = R.cam.ortho ? -VR_INF : 0.0f, t1 = VR_INF;
+        for (int a = 0; a < 3; ++a) {
+            const float oa = ff_to_f(o[a]), da = d[a].hi;
+            if (da != 0.0f) {
+                const float u = (-0.5f - oa) / da, v = (N[a] - 0.5f - oa) / da;
+                t0 = fmaxf(t0, fminf(u, v));
+                t1 = fminf(t1, fmaxf(u, v));
+            } else if (oa < -0.5f || oa > N[a] - 0.5f) {
+                t1 = -VR_INF;
+            }
+        }
+        best = fmaxf(best, t1 - t0);
+    }
+    const uint32_t c = (uint32_t)fminf(best / ff_to_f(R.step), 1.0e9f) + 16u;
+    const int lg = 31 - __builtin_clz(c);  // >= 4
+    const int b = 4 * lg + (int)((c >> (lg - 2)) & 3u) - 16;
+    return min(max(b, 0), VR_NBUCKET - 1);
+}
+
+// hist[0..127]: items per bucket, hist[128..255]: fill cursors
+__global__ void k_order_clear(unsigned* hist) {
+    if (threadIdx.x < 2 * VR_NBUCKET) hist[threadIdx.x] = 0u;
+}
+
+__device__ __forceinline__ void order_offsets(const unsigned* hist, unsigned* off) {
+    // off[b] = items in buckets above b (descending cost)
+    if (threadIdx.x == 0) {
+        unsigned acc = 0;
+        for (int b = VR_NBUCKET - 1; b >= 0; --b) {
+            off[b] = acc;
+            acc += hist[b];
+        }
+    }
+    __syncthreads();
+}
+
+__global__ void k_order_count_one(const DevReq R, int n, unsigned* hist) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) atomicAdd(&hist[tile_bucket(R, i)], 1u);
+}
+
+__global__ void k_order_scatter_one(const DevReq R, int n, unsigned* hist, int* order) {
+    __shared__ unsigned off[VR_NBUCKET];
+    order_offsets(hist, off);
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) {
+        const int b = tile_bucket(R, i);
+        order[off[b] + atomicAdd(&hist[VR_NBUCKET + b], 1u)] = i;
+    }
+}
+
+__global__ void k_order_count_batch(const DevReq* __restrict__ reqs, const DevItem* __restrict__ items,
+                                    const int* __restrict__ nitems, unsigned* hist) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < *nitems) {
+        const DevItem it = items[i];
+        atomicAdd(&hist[tile_bucket(reqs[it.req], it.tile)], 1u);
+    }
+}
+
+__global__ void k_order_scatter_batch(const DevReq* __restrict__ reqs, const DevItem* __restrict__ items,
+                                      const int* __restrict__ nitems, unsigned* hist,
+                                      DevItem* __restrict__ sorted) {
+    __shared__ unsigned off[VR_NBUCKET];
+    order_offsets(hist, off);
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < *nitems) {
+        const DevItem it = items[i];
+        const int b = tile_bucket(reqs[it.req], it.tile);
+        sorted[off[b] + atomicAdd(&hist[VR_NBUCKET + b], 1u)] = it;
+    }
 }
 
 __global__ void k_reset_head(unsigned* head) {
@@ -1238,39 +1326,52 @@ hipError_t vr_launch_classify(const float* cell_minmax, uint64_t* mask, uint32_t
 }
 
 template <int MODE, int DT, int INTERP>
-static hipError_t launch_r(const DevReq& R, DevCounters* cnt, hipStream_t s) {
+static hipError_t launch_r(const DevReq& R, const int* order, DevCounters* cnt, hipStream_t s) {
     const int grid = R.tiles_x * R.tiles_y;
     const size_t lds = (MODE == 0 ? (size_t)R.tf.n * 32 : 0) + 2 * (size_t)R.box_bytes;
-    hipLaunchKernelGGL((k_render<MODE, DT, INTERP>), dim3(grid), dim3(VR_WG), lds, s, R, cnt);
+    hipLaunchKernelGGL((k_render<MODE, DT, INTERP>), dim3(grid), dim3(VR_WG), lds, s, R, order, cnt);
     return hipGetLastError();
 }
 
-hipError_t vr_launch_render(const DevReq& R, DevCounters* cnt, hipStream_t s) {
+hipError_t vr_launch_render(const DevReq& R, int* order, unsigned* hist, DevCounters* cnt,
+                            hipStream_t s) {
+    const int n = R.tiles_x * R.tiles_y;
+    const int ob = (n + 255) / 256;
+    hipLaunchKernelGGL(k_order_clear, dim3(1), dim3(2 * VR_NBUCKET), 0, s, hist);
+    hipLaunchKernelGGL(k_order_count_one, dim3(ob), dim3(256), 0, s, R, n, hist);
+    hipLaunchKernelGGL(k_order_scatter_one, dim3(ob), dim3(256), 0, s, R, n, hist, order);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
     const int key = R.mode * 100 + R.cube.dtype * 10 + R.interp;
     switch (key) {
-        case 0: return launch_r<0, 0, 0>(R, cnt, s);
-        case 1: return launch_r<0, 0, 1>(R, cnt, s);
-        case 10: return launch_r<0, 1, 0>(R, cnt, s);
-        case 11: return launch_r<0, 1, 1>(R, cnt, s);
-        case 20: return launch_r<0, 2, 0>(R, cnt, s);
-        case 21: return launch_r<0, 2, 1>(R, cnt, s);
-        case 100: return launch_r<1, 0, 0>(R, cnt, s);
-        case 101: return launch_r<1, 0, 1>(R, cnt, s);
-        case 110: return launch_r<1, 1, 0>(R, cnt, s);
-        case 111: return launch_r<1, 1, 1>(R, cnt, s);
-        case 120: return launch_r<1, 2, 0>(R, cnt, s);
-        case 121: return launch_r<1, 2, 1>(R, cnt, s);
+        case 0: return launch_r<0, 0, 0>(R, order, cnt, s);
+        case 1: return launch_r<0, 0, 1>(R, order, cnt, s);
+        case 10: return launch_r<0, 1, 0>(R, order, cnt, s);
+        case 11: return launch_r<0, 1, 1>(R, order, cnt, s);
+        case 20: return launch_r<0, 2, 0>(R, order, cnt, s);
+        case 21: return launch_r<0, 2, 1>(R, order, cnt, s);
+        case 100: return launch_r<1, 0, 0>(R, order, cnt, s);
+        case 101: return launch_r<1, 0, 1>(R, order, cnt, s);
+        case 110: return launch_r<1, 1, 0>(R, order, cnt, s);
+        case 111: return launch_r<1, 1, 1>(R, order, cnt, s);
+        case 120: return launch_r<1, 2, 0>(R, order, cnt, s);
+        case 121: return launch_r<1, 2, 1>(R, order, cnt, s);
         default: return hipErrorInvalidValue;
     }
 }
 
 hipError_t vr_launch_batch(const DevReq* reqs, const DevItem* items, const int* nitems,
-                           unsigned* head, DevCounters* cnt, size_t lds_bytes, int grid,
-                           hipStream_t s) {
+                           int items_cap, DevItem* sorted, unsigned* hist, unsigned* head,
+                           DevCounters* cnt, size_t lds_bytes, int grid, hipStream_t s) {
+    const int ob = (items_cap + 255) / 256;
+    hipLaunchKernelGGL(k_order_clear, dim3(1), dim3(2 * VR_NBUCKET), 0, s, hist);
+    hipLaunchKernelGGL(k_order_count_batch, dim3(ob), dim3(256), 0, s, reqs, items, nitems, hist);
+    hipLaunchKernelGGL(k_order_scatter_batch, dim3(ob), dim3(256), 0, s, reqs, items, nitems, hist,
+                       sorted);
     hipLaunchKernelGGL(k_reset_head, dim3(1), dim3(64), 0, s, head);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_render_batch, dim3(grid), dim3(VR_WG), lds_bytes, s, reqs, items, nitems,
-                       head, cnt);
+    hipLaunchKernelGGL(k_render_batch, dim3(grid), dim3(VR_WG), lds_bytes, s, reqs,
+                       (const DevItem*)sorted, nitems, head, cnt);
     return hipGetLastError();
 }

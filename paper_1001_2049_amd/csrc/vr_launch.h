@@ -31,11 +31,14 @@ hipError_t vr_launch_classify(const float* cell_minmax, uint64_t* mask, uint32_t
                               int Bx, int By, int Bz, int mode, float clip, float scale,
                               float bias, int n, const int* kpos, hipStream_t s);
 
-// One image, one workgroup per 32x16 tile.
-hipError_t vr_launch_render(const DevReq& R, DevCounters* cnt, hipStream_t s);
+// One image, one workgroup per 32x16 tile, dispatched most expensive tile
+// first.  order: device scratch of tiles_x * tiles_y ints; hist: 256 words.
+hipError_t vr_launch_render(const DevReq& R, int* order, unsigned* hist, DevCounters* cnt,
+                            hipStream_t s);
 
 // Many images in one persistent launch over a (request, tile) work list of
-// *nitems entries (read on the device, so a captured launch serves any count).
+// *nitems entries (read on the device, so a captured launch serves any count),
+// reordered most expensive first into `sorted` (items_cap entries); hist: 256 words.
 hipError_t vr_launch_batch(const DevReq* reqs, const DevItem* items, const int* nitems,
-                           unsigned* head, DevCounters* cnt, size_t lds_bytes, int grid,
-                           hipStream_t s);
+                           int items_cap, DevItem* sorted, unsigned* hist, unsigned* head,
+                           DevCounters* cnt, size_t lds_bytes, int grid, hipStream_t s);
