@@ -36,7 +36,7 @@ def cpu_threads():
     return max(1, min(n, 16))
 
 
-def cpu_baseline(vol, tf, wl, cams, W, H, mode, budget_s=12.0, max_views=4):
+def cpu_baseline(vol, tf, wl, cams, W, H, mode, budget_s=12.0, max_views=16):
     """The FP64 reference timed on the host cores over whole frames until ~budget_s."""
     import numpy as np
 

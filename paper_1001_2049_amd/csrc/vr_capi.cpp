@@ -13,6 +13,8 @@
 namespace vrh {
 
 static thread_local std::string g_err;
+// step in progress, named in the message of an unexpected exception
+static thread_local const char* g_stage = "";
 
 void set_error(const std::string& msg) { g_err = msg; }
 
@@ -240,7 +242,11 @@ static vr_status get_mask(Ctx* c, Cube* cube, int mode, Tf* tf, float clip_s, hi
         }
     }
     MaskEntry* e = nullptr;
-    if (cube->masks.size() < 8) {
+    // evict the least recently used entry that the launch being built does not use
+    MaskEntry* lru = nullptr;
+    for (auto& m : cube->masks)
+        if (m.stamp <= c->launch_stamp && (!lru || m.stamp < lru->stamp)) lru = &m;
+    if (cube->masks.size() < 8 || !lru) {
         cube->masks.emplace_back();
         e = &cube->masks.back();
         vr_status st = dev_alloc(c, e->buf, (uint64_t)cube->nslots * 8, true);
@@ -255,8 +261,7 @@ static vr_status get_mask(Ctx* c, Cube* cube, int mode, Tf* tf, float clip_s, hi
         st = ensure_event(e->last_use);
         if (st != VR_OK) return st;
     } else {
-        e = &*std::min_element(cube->masks.begin(), cube->masks.end(),
-                               [](const MaskEntry& a, const MaskEntry& b) { return a.stamp < b.stamp; });
+        e = lru;
         // the entry may still be read by queued work on another stream
         vr_status st = hip_check(hipStreamWaitEvent(s, e->last_use, 0), "hipStreamWaitEvent");
         if (st != VR_OK) return st;
@@ -476,6 +481,7 @@ static int pow2_at_least(int v, int lo) {
 }
 
 static vr_status grow_batch(Ctx* c, BatchBufs& bb, int nreq, int nitems) {
+    g_stage = "batch buffers";
     vr_status st = ensure_event(bb.done);
     if (st != VR_OK) return st;
     // staging may still feed a queued copy
@@ -534,6 +540,7 @@ static vr_status enqueue_batch(Ctx* c, BatchBufs& bb, int count, int nitems, siz
     const size_t rq_bytes = (size_t)(use_graph ? bb.reqs_cap : count) * sizeof(DevReq);
     const size_t it_bytes = (size_t)(use_graph ? bb.items_cap : nitems) * sizeof(DevItem);
     const int grid = use_graph ? c->num_cu : std::max(1, std::min(nitems, c->num_cu));
+    g_stage = "batch enqueue";
     auto record = [&]() -> vr_status {
         vr_status st = hip_check(hipMemcpyAsync(bb.hdr.ptr, bb.pin_hdr, 16, hipMemcpyHostToDevice, s),
                                  "hipMemcpyAsync");
@@ -584,6 +591,8 @@ vr_status launch_requests(Ctx* c, BatchBufs& bb, const vr_request* reqs, int cou
     if (st != VR_OK) return st;
     int max_tf_n = 0, k = 0;
     std::vector<MaskEntry*> used((size_t)count, nullptr);
+    g_stage = "request set-up";
+    c->launch_stamp = c->mask_stamp;
     for (int r = 0; r < count; ++r) {
         const vr_request& q = reqs[r];
         Cube* cube = find_cube(c, q.cube);
@@ -606,6 +615,7 @@ vr_status launch_requests(Ctx* c, BatchBufs& bb, const vr_request* reqs, int cou
         st = enqueue_batch(c, bb, count, nitems, lds, dev_counters, s, use_graph);
         if (st != VR_OK) return st;
     }
+    g_stage = "batch completion";
     st = hip_check(hipEventRecord(bb.done, s), "hipEventRecord");
     if (st != VR_OK) return st;
     for (int r = 0; r < count; ++r) {
@@ -700,7 +710,8 @@ using namespace vrh;
         set_error("host allocation failed");                    \
         return VR_ENOMEM;                                       \
     } catch (const std::exception& ex) {                        \
-        set_error(std::string("internal error: ") + ex.what()); \
+        set_error(std::string("internal error in ") + g_stage +  \
+                  ": " + ex.what());                            \
         return VR_EINVAL;                                       \
     } catch (...) {                                             \
         set_error("internal error");                            \
@@ -1070,6 +1081,7 @@ vr_status vr_render(vr_ctx ctx, vr_cube cube, const vr_render_params* params, vo
         hipStream_t s = (hipStream_t)hip_stream;
         DevReq R;
         MaskEntry* me = nullptr;
+        c->launch_stamp = c->mask_stamp;
         st = build_request(c, cu, tf, c->clip, c->camera, *params, out_dev, s, R, &me);
         if (st != VR_OK) return st;
         DevCounters* dc = nullptr;
@@ -1186,6 +1198,7 @@ vr_status vr_render_batch(vr_ctx ctx, const vr_request* reqs, int32_t count, voi
         hipStream_t s = (hipStream_t)hip_stream;
         DevCounters* dc = nullptr;
         hipEvent_t e0 = nullptr, e1 = nullptr;
+        g_stage = "batch counters";
         if (stats) {
             st = ensure_counters(c, count);
             if (st != VR_OK) return st;
@@ -1198,6 +1211,7 @@ vr_status vr_render_batch(vr_ctx ctx, const vr_request* reqs, int32_t count, voi
         }
         st = launch_requests(c, c->batch, reqs, count, nullptr, s, dc);
         if (st != VR_OK) return st;
+        g_stage = "batch statistics";
         if (stats) {
             st = hip_check(hipEventRecord(e1, s), "hipEventRecord");
             if (st == VR_OK) st = hip_check(hipEventSynchronize(e1), "batch render");

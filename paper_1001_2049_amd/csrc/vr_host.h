@@ -51,7 +51,7 @@ struct Cube {
     int row = 0;                    // elements per stored row
     uint64_t stride = 0;
     DevBuf pool, cellmm;
-    std::vector<MaskEntry> masks;
+    std::deque<MaskEntry> masks;    // deque: entries never move while requests point at them
     hipEvent_t last_use = nullptr;  // last work reading this cube
     int refs = 0;                   // queued serving requests
     uint64_t bytes() const;
@@ -105,6 +105,7 @@ struct Ctx {
     int32_t next_cube = 1, next_tf = 1;
     int64_t next_tf_version = 1;
     uint64_t mask_stamp = 0;
+    uint64_t launch_stamp = 0;  // mask_stamp when the current launch began: newer entries are in use
 
     // scratch for single renders / batches
     DevBuf counters;             // DevCounters x capacity

@@ -378,9 +378,10 @@ __device__ __forceinline__ bool composite(const DevReq& R, const float* __restri
                                           bool last, const Ray& ray, Accum& acc) {
     float u = __builtin_fmaf(v, R.tf.scale, R.tf.bias);
     u = __builtin_amdgcn_fmed3f(u, 0.0f, (float)(R.tf.n - 1));
-    const float fl = fminf(floorf(u), (float)(R.tf.n - 2));
-    const float g = u - fl;
-    const float4* row = (const float4*)(tfl + 8 * (int)fl);
+    // u >= 0: truncation is the floor; at u = n - 1 the last row is taken with
+    // weight 0 (its difference entry is zero), which gives that row exactly
+    const float g = __builtin_amdgcn_fractf(u);
+    const float4* row = (const float4*)(tfl + 8 * (int)u);
     const float4 r0 = row[0], dr = row[1];
     float kap = __builtin_fmaf(g, dr.w, r0.w);
     kap = v < R.tf.clip ? 0.0f : kap;
@@ -576,19 +577,21 @@ __device__ __forceinline__ int wave_max(int v) {
     return v;
 }
 
+// Voxel index and weights of a position in box-local coordinates: clamped to
+// [0, hi] (the cube's last voxel on the upper side; the box never starts below
+// a sample), so truncation is the floor.  Trilinear at q = N - 1 takes the last
+// voxel with weight 0 (its +1 neighbour is the edge-clamped apron).
 template <int INTERP>
-__device__ __forceinline__ void floor_idx(const float p[3], const float lo[3], const float hi[3],
-                                          int i[3], float w[3]) {
+__device__ __forceinline__ void floor_idx(const float p[3], const float hi[3], int i[3], float w[3]) {
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
-        const float q = __builtin_amdgcn_fmed3f(p[a], lo[a], hi[a]);
+        const float q = __builtin_amdgcn_fmed3f(p[a], 0.0f, hi[a]);
         if (INTERP == 1) {
-            const float f = floorf(q);
-            w[a] = q - f;
-            i[a] = (int)f;
+            w[a] = __builtin_amdgcn_fractf(q);
+            i[a] = (int)q;
         } else {
             w[a] = 0.0f;
-            i[a] = (int)floorf(q + 0.5f);
+            i[a] = (int)(q + 0.5f);
         }
     }
 }
@@ -889,9 +892,9 @@ __device__ __forceinline__ bool tile_march(const DevReq& R, const Ray& ray, cons
                 const int x = s.xa + min(c, ncd - 1) * CV;  // the pad slot repeats the last chunk
                 const int bxb = min(x >> 5, R.cube.bx - 1);
                 const int lx = x - 32 * bxb;
-                const uint32_t slot = ((uint32_t)(gz >> 5) * (uint32_t)R.cube.by + (uint32_t)(gy >> 5)) *
-                                          (uint32_t)R.cube.bx + (uint32_t)bxb;
-                const uint32_t off = (uint32_t)((((gz & 31) * VR_BRICK_APRON + (gy & 31)) * R.cube.row + lx) * ELEM);
+                const uint32_t slot = __umul24(__umul24(gz >> 5, R.cube.by) + (gy >> 5), R.cube.bx) + bxb;
+                const uint32_t off = __umul24(__umul24(gz & 31, VR_BRICK_APRON) + (gy & 31), R.cube.row * ELEM) +
+                                     lx * ELEM;
                 const uint8_t* src = R.cube.pool + ((uint64_t)slot * bstride + off);
                 __builtin_amdgcn_global_load_lds((const void*)src,
                                                  (__attribute__((address_space(3))) void*)(buf + q0 * 16),
@@ -950,7 +953,7 @@ __device__ __forceinline__ bool tile_march(const DevReq& R, const Ray& ray, cons
             if (!sh.any[it & 7]) {
                 nskip += (unsigned)cnt_s;
             } else {
-                float A[3], cl[3], ch[3];
+                float A[3], ch[3];
                 {
                     const float kf = (float)ks + 0.5f;
                     ff sk = two_prod(kf, R.step.hi);
@@ -958,7 +961,6 @@ __device__ __forceinline__ bool tile_march(const DevReq& R, const Ray& ray, cons
 #pragma unroll
                     for (int a = 0; a < 3; ++a) {
                         A[a] = anchor_axis(E[a], ray.d[a], sk, s0.lo[a]);
-                        cl[a] = (float)(-s0.lo[a]);
                         ch[a] = (float)(N[a] - 1 - s0.lo[a]);
                     }
                 }
@@ -971,7 +973,7 @@ __device__ __forceinline__ bool tile_march(const DevReq& R, const Ray& ray, cons
                                             __builtin_fmaf(jf, ray.dd[2], A[2])};
                         int i[3];
                         float w[3];
-                        floor_idx<INTERP>(p, cl, ch, i, w);
+                        floor_idx<INTERP>(p, ch, i, w);
                         const float v = fetch(i, w);
                         ++nexec;
                         if (MODE == 1) {
@@ -988,8 +990,8 @@ __device__ __forceinline__ bool tile_march(const DevReq& R, const Ray& ray, cons
                     const int sy = pitch, sz = pitch * s0.dim[1];
                     const int xoff = s0.lo[0] - s0.xa;
                     run([&](const int* i, const float* w) {
-                        return interp_box<DT, INTERP>(box, (i[2] * s0.dim[1] + i[1]) * pitch + (i[0] + xoff),
-                                                      sy, sz, w[0], w[1], w[2]);
+                        const int idx = (int)__umul24(__umul24(i[2], s0.dim[1]) + i[1], pitch) + i[0] + xoff;
+                        return interp_box<DT, INTERP>(box, idx, sy, sz, w[0], w[1], w[2]);
                     });
                 } else {
                     run([&](const int* i, const float* w) {
@@ -1144,6 +1146,8 @@ __global__ __launch_bounds__(VR_WG) void k_render(const DevReq R, const int* __r
 #define VR_NBUCKET 128
 
 __device__ __forceinline__ int tile_bucket(const DevReq& R, int tile) {
+    // plain float is enough for an estimate
+    const DevCam& C = R.cam;
     const int tx = tile % R.tiles_x, ty = tile / R.tiles_x;
     const float xa = (float)(tx * VR_TW) + 0.5f, xb = (float)min(tx * VR_TW + VR_TW, R.W) - 0.5f;
     const float ya = (float)(ty * VR_TH) + 0.5f, yb = (float)min(ty * VR_TH + VR_TH, R.H) - 0.5f;
@@ -1152,22 +1156,33 @@ __device__ __forceinline__ int tile_bucket(const DevReq& R, int tile) {
     for (int k = 0; k < 5; ++k) {
         const float fi = k == 4 ? 0.5f * (xa + xb) : ((k & 1) ? xb : xa);
         const float fj = k == 4 ? 0.5f * (ya + yb) : ((k & 2) ? yb : ya);
-        ff o[3], d[3];
-        ray_dir(R.cam, fi, fj, o, d);
-        float t0 = R.cam.ortho ? -VR_INF : 0.0f, t1 = VR_INF;
+        float o[3], d[3], n2 = 0.0f;
         for (int a = 0; a < 3; ++a) {
-            const float oa = ff_to_f(o[a]), da = d[a].hi;
+            const float e = __builtin_fmaf(C.dx[a].hi, fi, __builtin_fmaf(C.dy[a].hi, fj, 0.0f));
+            if (C.ortho) {
+                o[a] = C.o[a].hi + e;
+                d[a] = C.dir[a].hi;
+            } else {
+                o[a] = C.o[a].hi;
+                d[a] = C.base[a].hi + e;
+                n2 = __builtin_fmaf(d[a], d[a], n2);
+            }
+        }
+        const float inv = C.ortho ? 1.0f : 1.0f / __builtin_sqrtf(n2);
+        float t0 = C.ortho ? -VR_INF : 0.0f, t1 = VR_INF;
+        for (int a = 0; a < 3; ++a) {
+            const float da = d[a] * inv;
             if (da != 0.0f) {
-                const float u = (-0.5f - oa) / da, v = (N[a] - 0.5f - oa) / da;
+                const float u = (-0.5f - o[a]) / da, v = (N[a] - 0.5f - o[a]) / da;
                 t0 = fmaxf(t0, fminf(u, v));
                 t1 = fminf(t1, fmaxf(u, v));
-            } else if (oa < -0.5f || oa > N[a] - 0.5f) {
+            } else if (o[a] < -0.5f || o[a] > N[a] - 0.5f) {
                 t1 = -VR_INF;
             }
         }
         best = fmaxf(best, t1 - t0);
     }
-    const uint32_t c = (uint32_t)fminf(best / ff_to_f(R.step), 1.0e9f) + 16u;
+    const uint32_t c = (uint32_t)fminf(best / R.step.hi, 1.0e9f) + 16u;
     const int lg = 31 - __builtin_clz(c);  // >= 4
     const int b = 4 * lg + (int)((c >> (lg - 2)) & 3u) - 16;
     return min(max(b, 0), VR_NBUCKET - 1);

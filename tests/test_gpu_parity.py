@@ -277,3 +277,29 @@ def test_full_cube_sampled_pixels(R, full_workload, mode):
             assert st["samples_exec"] <= st["samples_nominal"]
     finally:
         R.release(cube)
+
+
+def test_batch_with_many_fresh_skip_masks(R, tiny, tiny_cube):
+    """One batch whose requests need more skip masks on one cube than the cache
+    holds (EA and MIP, ten noise clips): every image equals its single render."""
+    import torch
+    wl, vol, tf = tiny
+    R.set_transfer_function(tf, wl.v0, wl.v1)
+    cam = synth.orbit_camera(64, 64, 128, 1.3, 0.4)
+    reqs, outs, singles = [], [], []
+    for q in range(10):
+        clip = 2.0 + 0.4 * q
+        for mode in ("ea", "mip"):
+            out = R.output(96, 80, mode)
+            reqs.append(R.request(tiny_cube, cam, 96, 80, out, mode=mode, clip=clip))
+            outs.append(out)
+    R.render_batch(reqs)
+    torch.cuda.synchronize()
+    got = [to_np(o).copy() for o in outs]
+    R.set_camera(cam)
+    for q in range(10):
+        R.set_noise_clip(2.0 + 0.4 * q, 1.0)
+        for mode in ("ea", "mip"):
+            singles.append(to_np(R.render(tiny_cube, 96, 80, mode=mode)).copy())
+    for a, b in zip(got, singles):
+        assert np.array_equal(a.view(np.uint32), b.view(np.uint32))
