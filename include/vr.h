@@ -139,13 +139,17 @@ typedef struct {
     uint64_t brick_stride;      /* bytes between brick slots */
     uint64_t aux_bytes;         /* device bytes of tables and statistics */
     float vmin, vmax;           /* range of stored values times sigma_scale */
-    int32_t row_elems;          /* stored elements per brick row (>= brick+1, 16-byte multiple) */
+    int32_t x_chunks;           /* 16-byte chunks of x per slot row (9 float32, 5 16-bit) */
     int32_t reserved;
     /* device pointers, for inspection: */
     const void* pool;           /* brick slots; slot of brick (bx,by,bz) is
-                                   (bz*bricks_y + by)*bricks_x + bx; inside a slot, local
-                                   voxel (lx,ly,lz) in [0,brick]^3 is element
-                                   (lz*(brick+1) + ly)*row_elems + lx, edge-clamped */
+                                   (bz*bricks_y + by)*bricks_x + bx.  A slot holds local voxels
+                                   lx < 16*x_chunks/elem, ly < 36, lz < 34, each the
+                                   edge-clamped value of global voxel (32bx+lx, 32by+ly, 32bz+lz),
+                                   in 128-byte lines of one x chunk by 4 y by 2 z: with
+                                   cv = 16/elem elements per chunk, voxel (lx,ly,lz) is element
+                                   (((lz/2)*9 + ly/4)*x_chunks + lx/cv)*8*cv
+                                   + ((lz%2)*4 + ly%4)*cv + lx%cv */
     const float* cell_minmax;   /* per slot: 64 cells x (min, max) of stored values; cell
                                    (cx,cy,cz) in [0,3]^3 is entry (cz*4 + cy)*4 + cx and covers
                                    local voxels [8c, 8c+8] per axis */

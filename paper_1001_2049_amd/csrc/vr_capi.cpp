@@ -304,7 +304,7 @@ vr_status build_request(Ctx* c, Cube* cube, Tf* tf, float clip, const vr_camera&
     }
     R.cube.pool = (const uint8_t*)cube->pool.ptr;
     R.cube.stride = cube->stride;
-    R.cube.row = cube->row;
+    R.cube.xch = cube->xch;
     R.cube.nx = (int)cube->nx;
     R.cube.ny = (int)cube->ny;
     R.cube.nz = (int)cube->nz;
@@ -853,10 +853,8 @@ vr_status vr_cube_upload(vr_ctx ctx, const void* src, int32_t src_dtype, int32_t
             return VR_EINVAL;
         }
         cube->nslots = (int)ns;
-        const uint64_t elem = storage == VR_F32 ? 4 : 2;
-        cube->row = VR_ROW(storage);
-        cube->stride =
-            ((uint64_t)VR_BRICK_APRON * VR_BRICK_APRON * cube->row * elem + 255) & ~uint64_t(255);
+        cube->xch = VR_XCH(storage);
+        cube->stride = ((uint64_t)VR_SLOT_ZP * VR_SLOT_YG * cube->xch * 128 + 255) & ~uint64_t(255);
         auto cleanup = [&]() {
             dev_free(c, cube->pool, true);
             dev_free(c, cube->cellmm, true);
@@ -873,7 +871,8 @@ vr_status vr_cube_upload(vr_ctx ctx, const void* src, int32_t src_dtype, int32_t
         const uint64_t plane = (uint64_t)nx * ny * selem;
         DevBuf stage;
         if (!src_on_device) {
-            st = dev_alloc(c, stage, plane * (uint64_t)std::min<int64_t>(nz, VR_BRICK_APRON), false);
+            // a brick layer reads planes z0 .. z0 + 33 (apron and padding, edge-clamped)
+            st = dev_alloc(c, stage, plane * (uint64_t)std::min<int64_t>(nz, 2 * VR_SLOT_ZP), false);
             if (st != VR_OK) {
                 cleanup();
                 return st;
@@ -881,7 +880,7 @@ vr_status vr_cube_upload(vr_ctx ctx, const void* src, int32_t src_dtype, int32_t
         }
         for (int bz = 0; bz < cube->Bz && st == VR_OK; ++bz) {
             const int64_t z0 = (int64_t)bz * VR_BRICK;
-            const int64_t z1 = std::min<int64_t>(z0 + VR_BRICK_APRON, nz);
+            const int64_t z1 = std::min<int64_t>(z0 + 2 * VR_SLOT_ZP, nz);
             const void* slab = src;
             int64_t z_first = 0;
             if (!src_on_device) {
@@ -894,7 +893,7 @@ vr_status vr_cube_upload(vr_ctx ctx, const void* src, int32_t src_dtype, int32_t
             }
             st = hip_check(vr_launch_brick_build(src_kind, storage, slab, nx, ny, nz, z_first, bz,
                                                  cube->Bx, cube->By, (uint8_t*)cube->pool.ptr,
-                                                 cube->stride, cube->row, (float*)cube->cellmm.ptr,
+                                                 cube->stride, cube->xch, (float*)cube->cellmm.ptr,
                                                  (float)sigma_scale, s),
                            "brick build launch");
         }
@@ -962,7 +961,7 @@ vr_status vr_cube_get_info(vr_ctx ctx, vr_cube cube, vr_cube_info* out) {
         out->brick_stride = cu->stride;
         out->aux_bytes = cu->bytes() - cu->pool.bytes;
         out->pool = cu->pool.ptr;
-        out->row_elems = cu->row;
+        out->x_chunks = cu->xch;
         out->cell_minmax = (const float*)cu->cellmm.ptr;
         (void)hipSetDevice(c->device);
         std::vector<float> mm((size_t)cu->nslots * 2 * VR_CELLS_PER_BRICK);

@@ -27,16 +27,22 @@ struct ff {
 #define VR_NWAVE (VR_WG / 64)
 #define VR_LDS_MAX 163840           // LDS per workgroup on gfx950
 #define VR_LDS_STATIC 4096          // reserved for the kernels' static LDS
-// Stored rows are padded to a multiple of 16 bytes so that any 16-byte chunk
-// starting at a local x that is a multiple of 4 (float) or 8 (16-bit) stays in
-// its row and is 16-byte aligned.
-#define VR_ROW_F32 36
-#define VR_ROW_16 40
-#define VR_ROW(dt) ((dt) == 0 ? VR_ROW_F32 : VR_ROW_16)
+// Brick slot layout.  A slot stores local voxels x in [0, 4*xch), y in [0, 36),
+// z in [0, 34) (the brick's 33^3 with its apron, padded), each the
+// edge-clamped value of its global position.  Memory is cut into 128-byte
+// lines; a line holds one 16-byte chunk of x (4 float or 8 16-bit values) for
+// 4 consecutive y and 2 consecutive z, so that a box of any orientation copied
+// chunk by chunk uses whole lines.  The element offset of (lx, ly, lz) is
+// X(lx) + Y(ly) + Z(lz) with
+//   X = (lx / CV) * 8 CV + lx % CV,  Y = (ly / 4) * xch * 8 CV + (ly % 4) * CV,
+//   Z = (lz / 2) * 9 * xch * 8 CV + (lz % 2) * 4 CV.
+#define VR_SLOT_YG 9                // groups of 4 rows per slot
+#define VR_SLOT_ZP 17               // pairs of planes per slot
+#define VR_XCH(dt) ((dt) == 0 ? 9 : 5)   // x chunks per row
+#define VR_CVE(dt) ((dt) == 0 ? 4 : 8)   // elements per 16-byte chunk
 
 // Cube as seen by the render kernels.  Slot of brick (bx, by, bz) is the
-// linear index (bz * by_count + by) * bx_count + bx; voxel (lx, ly, lz) of a
-// slot sits at element (lz * 33 + ly) * row + lx.
+// linear index (bz * by_count + by) * bx_count + bx.
 struct DevCube {
     const uint8_t* pool;            // brick slots
     const uint64_t* mask;           // per slot: bit c set if cell c may contribute
@@ -45,7 +51,7 @@ struct DevCube {
     int32_t nx, ny, nz;
     int32_t bx, by, bz;             // bricks per axis
     int32_t dtype;                  // 0 f32, 1 f16, 2 bf16
-    int32_t row;                    // elements per stored row
+    int32_t xch;                    // x chunks per slot row
 };
 
 // Transfer function: rows[2i] = row i (r, g, b, kappa), rows[2i+1] = row i+1 - row i.

@@ -48,7 +48,7 @@ struct Cube {
     double sigma = 1.0;
     int Bx = 0, By = 0, Bz = 0;
     int nslots = 0;
-    int row = 0;                    // elements per stored row
+    int xch = 0;                    // x chunks per slot row
     uint64_t stride = 0;
     DevBuf pool, cellmm;
     std::deque<MaskEntry> masks;    // deque: entries never move while requests point at them

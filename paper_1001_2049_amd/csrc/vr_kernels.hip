@@ -78,7 +78,7 @@ __device__ __forceinline__ uint16_t enc_f16(float x) {
 template <int SRC, int DST>
 __global__ __launch_bounds__(VR_BB_WG) void k_brick_build(
     const void* __restrict__ src, int64_t nx, int64_t ny, int64_t nz, int64_t z_first, int bz,
-    int Bx, int By, uint8_t* __restrict__ pool, uint64_t stride, int row,
+    int Bx, int By, uint8_t* __restrict__ pool, uint64_t stride, int xch,
     float* __restrict__ cell_minmax, float sigma) {
     __shared__ float vals[VR_BRICK_VOX];
     __shared__ float cmin[VR_CELLS_PER_BRICK], cmax[VR_CELLS_PER_BRICK];
@@ -88,9 +88,13 @@ __global__ __launch_bounds__(VR_BB_WG) void k_brick_build(
     DT* dst = (DT*)(pool + slot * stride);
     const int64_t x0 = (int64_t)bxi * VR_BRICK, y0 = (int64_t)byi * VR_BRICK,
                   z0 = (int64_t)bz * VR_BRICK;
-    const int nel = VR_BRICK_APRON * VR_BRICK_APRON * row;
+    constexpr int CV = DST == 0 ? 4 : 8;
+    const int nel = VR_SLOT_ZP * VR_SLOT_YG * xch * 8 * CV;
     for (int e = threadIdx.x; e < nel; e += VR_BB_WG) {
-        const int lx = e % row, ly = (e / row) % VR_BRICK_APRON, lz = e / (row * VR_BRICK_APRON);
+        // element e of the slot: chunk e / CV is word (e / CV) % 8 of line e / (8 CV)
+        const int sub = e % CV, q = e / CV, w = q & 7, L = q >> 3;
+        const int cx = L % xch, yg = (L / xch) % VR_SLOT_YG, zp = L / (xch * VR_SLOT_YG);
+        const int lx = cx * CV + sub, ly = yg * 4 + (w & 3), lz = zp * 2 + (w >> 2);
         int64_t gx = x0 + lx, gy = y0 + ly, gz = z0 + lz;
         gx = gx < nx - 1 ? gx : nx - 1;
         gy = gy < ny - 1 ? gy : ny - 1;
@@ -117,7 +121,8 @@ __global__ __launch_bounds__(VR_BB_WG) void k_brick_build(
             ((uint16_t*)dst)[e] = c;
             dec = Vox<DST>::dec(c);
         }
-        if (lx < VR_BRICK_APRON) vals[(lz * VR_BRICK_APRON + ly) * VR_BRICK_APRON + lx] = dec;
+        if (lx < VR_BRICK_APRON && ly < VR_BRICK_APRON && lz < VR_BRICK_APRON)
+            vals[(lz * VR_BRICK_APRON + ly) * VR_BRICK_APRON + lx] = dec;
     }
     __syncthreads();
     // 64 cells, 4 threads per cell; cell c covers local [8c, 8c+8] on each axis (9^3)
@@ -311,15 +316,28 @@ __device__ __forceinline__ ff sample_t(const DevReq& R, const Ray& ray, int k) {
     return t;
 }
 
-// Stored value of global voxel (gx, gy, gz) in the brick pool; its +x/+y/+z
-// neighbours are in the same slot thanks to the apron.
+// Element offsets of local voxel coordinates inside a slot (separable).
 template <int DT>
-__device__ __forceinline__ const typename Vox<DT>::T* pool_ptr(const DevCube& c, int gx, int gy,
-                                                               int gz) {
-    const uint64_t slot = ((uint64_t)(gz >> 5) * c.by + (gy >> 5)) * c.bx + (gx >> 5);
-    const int idx = ((gz & 31) * VR_BRICK_APRON + (gy & 31)) * c.row + (gx & 31);
-    return (const typename Vox<DT>::T*)(c.pool + slot * c.stride) + idx;
+__device__ __forceinline__ int slot_x(int lx) {
+    constexpr int CV = DT == 0 ? 4 : 8;
+    return (lx / CV) * 8 * CV + lx % CV;
 }
+template <int DT>
+__device__ __forceinline__ int slot_y(int ly, int xch) {
+    constexpr int CV = DT == 0 ? 4 : 8;
+    return (ly >> 2) * xch * 8 * CV + (ly & 3) * CV;
+}
+template <int DT>
+__device__ __forceinline__ int slot_z(int lz, int xch) {
+    constexpr int CV = DT == 0 ? 4 : 8;
+    return (lz >> 1) * VR_SLOT_YG * xch * 8 * CV + (lz & 1) * 4 * CV;
+}
+
+// Interpolated value at local voxel (lx, ly, lz) of a slot with weights w;
+// the +1 neighbours are in the same slot thanks to the apron.
+template <int DT, int INTERP>
+__device__ __forceinline__ float slot_value(const typename Vox<DT>::T* base, int xch, int lx, int ly,
+                                            int lz, float w0, float w1, float w2);
 
 // Trilinear interpolation of the 8 corners (x, then y, then z).
 __device__ __forceinline__ float trilerp(float c000, float c100, float c010, float c110, float c001,
@@ -343,6 +361,27 @@ __device__ __forceinline__ float interp_at(P bp, int sy, int sz, float w0, float
                        Vox<DT>::dec(bp[sz + sy]), Vox<DT>::dec(bp[sz + sy + 1]), w0, w1, w2);
     }
     return Vox<DT>::dec(bp[0]);
+}
+
+template <int DT, int INTERP>
+__device__ __forceinline__ float slot_value(const typename Vox<DT>::T* base, int xch, int lx, int ly,
+                                            int lz, float w0, float w1, float w2) {
+    const int x0 = slot_x<DT>(lx), y0 = slot_y<DT>(ly, xch), z0 = slot_z<DT>(lz, xch);
+    if (INTERP == 0) return Vox<DT>::dec(base[x0 + y0 + z0]);
+    const int x1 = slot_x<DT>(lx + 1), y1 = slot_y<DT>(ly + 1, xch), z1 = slot_z<DT>(lz + 1, xch);
+    return trilerp(Vox<DT>::dec(base[z0 + y0 + x0]), Vox<DT>::dec(base[z0 + y0 + x1]),
+                   Vox<DT>::dec(base[z0 + y1 + x0]), Vox<DT>::dec(base[z0 + y1 + x1]),
+                   Vox<DT>::dec(base[z1 + y0 + x0]), Vox<DT>::dec(base[z1 + y0 + x1]),
+                   Vox<DT>::dec(base[z1 + y1 + x0]), Vox<DT>::dec(base[z1 + y1 + x1]), w0, w1, w2);
+}
+
+// Value of global voxel position (gx, gy, gz) (floor indices) from the pool.
+template <int DT, int INTERP>
+__device__ __forceinline__ float pool_value(const DevCube& c, int gx, int gy, int gz, float w0,
+                                            float w1, float w2) {
+    const uint32_t slot = __umul24(__umul24(gz >> 5, c.by) + (gy >> 5), c.bx) + (gx >> 5);
+    const typename Vox<DT>::T* base = (const typename Vox<DT>::T*)(c.pool + (uint64_t)slot * c.stride);
+    return slot_value<DT, INTERP>(base, c.xch, gx & 31, gy & 31, gz & 31, w0, w1, w2);
 }
 
 // Value at element idx of a box staged in LDS, strides (1, sy, sz) elements.
@@ -433,7 +472,6 @@ __device__ __forceinline__ void render_lane_direct(const DevReq& R, const int px
     }
     const int N[3] = {R.cube.nx, R.cube.ny, R.cube.nz};
     const int B[3] = {R.cube.bx, R.cube.by, R.cube.bz};
-    const int sy = R.cube.row, sz = VR_BRICK_APRON * R.cube.row;
     float inv_dd[3];
 #pragma unroll
     for (int a = 0; a < 3; ++a) inv_dd[a] = ray.dd[a] != 0.0f ? 1.0f / ray.dd[a] : 0.0f;
@@ -521,8 +559,7 @@ __device__ __forceinline__ void render_lane_direct(const DevReq& R, const int px
             j += jump;
             continue;
         }
-        const int idx = (i2 * VR_BRICK_APRON + i1) * sy + i0;
-        const float v = interp_at<DT, INTERP>((const VT*)base + idx, sy, sz, w0, w1, w2);
+        const float v = slot_value<DT, INTERP>((const VT*)base, R.cube.xch, i0, i1, i2, w0, w1, w2);
         ++nexec;
         ++j;
         if (MODE == 1) {
@@ -869,45 +906,64 @@ __device__ __forceinline__ bool tile_march(const DevReq& R, const Ray& ray, cons
         }
         w0w = R.cube.cellbits[wa];
     };
-    // copy a slab's box into buffer `which`: LDS slot q (row-major over
-    // [z][y][x-chunk], np slots per row) receives 16 bytes at byte 16 q; each
-    // thread walks its slots q = tid + 512 k with incremental (chunk, row) indices
-    const uint32_t bstride = (uint32_t)R.cube.stride;
+    // Copy a slab's box into its LDS buffer: the box is row-major over
+    // [z][y][16-byte chunk] with np chunks per row, and global->LDS loads write
+    // 16 bytes per lane at consecutive LDS addresses, so each wave instruction
+    // moves rw = 64 / np whole rows (lane l: row l / np, chunk l % np; the
+    // x part of its source address stays fixed for the whole box).  Rows of
+    // more than 64 chunks go one row per instruction group.
     auto staged = [&](const Slab& s) { return s.elems <= (s.big ? 2 * cap : cap); };
+    const uint32_t bstride = (uint32_t)R.cube.stride;
+    auto row_src = [&](const Slab& s, int iy, int iz) -> const uint8_t* {
+        const int gy = min(s.lo[1] + iy, N[1] - 1), gz = min(s.lo[2] + iz, N[2] - 1);
+        const uint32_t slot_yz = __umul24(__umul24(gz >> 5, R.cube.by) + (gy >> 5), R.cube.bx);
+        const uint32_t off = (uint32_t)(slot_y<DT>(gy & 31, R.cube.xch) + slot_z<DT>(gz & 31, R.cube.xch)) * ELEM;
+        return R.cube.pool + ((uint64_t)slot_yz * bstride + off);
+    };
+    auto chunk_off = [&](const Slab& s, int c) -> uint64_t {
+        const int x = s.xa + min(c, s.nc - 1) * CV;  // pad slots repeat the last chunk
+        const int bxb = min(x >> 5, R.cube.bx - 1);
+        return (uint64_t)bxb * bstride + (uint32_t)(((x - 32 * bxb) / CV) * 128);
+    };
     auto box_dma = [&](const Slab& s) {
         if (s.S == 0 || s.elems == 0 || !staged(s)) return;
         uint8_t* buf = boxes + s.boff;
-        const int nc = s.np, d1 = s.dim[1], ncd = s.nc;
-        const int total = nc * d1 * s.dim[2];
-        const float inv_nc = 1.0f / (float)nc, inv_d1 = 1.0f / (float)d1;
-        const int row = div_small(tid, nc, inv_nc);
-        int c = tid - row * nc;
-        int iz = div_small(row, d1, inv_d1);
-        int iy = row - iz * d1;
-        const int qr = div_small(VR_WG, nc, inv_nc), qc = VR_WG - qr * nc;
-        const int dz = div_small(qr, d1, inv_d1), dy = qr - dz * d1;
-        for (int q0 = wave * 64; q0 < total; q0 += VR_WG) {
-            if (q0 + lane < total) {
-                const int gy = min(s.lo[1] + iy, N[1] - 1), gz = min(s.lo[2] + iz, N[2] - 1);
-                const int x = s.xa + min(c, ncd - 1) * CV;  // the pad slot repeats the last chunk
-                const int bxb = min(x >> 5, R.cube.bx - 1);
-                const int lx = x - 32 * bxb;
-                const uint32_t slot = __umul24(__umul24(gz >> 5, R.cube.by) + (gy >> 5), R.cube.bx) + bxb;
-                const uint32_t off = __umul24(__umul24(gz & 31, VR_BRICK_APRON) + (gy & 31), R.cube.row * ELEM) +
-                                     lx * ELEM;
-                const uint8_t* src = R.cube.pool + ((uint64_t)slot * bstride + off);
-                __builtin_amdgcn_global_load_lds((const void*)src,
-                                                 (__attribute__((address_space(3))) void*)(buf + q0 * 16),
-                                                 16, 0, 0);
+        const int np = s.np, d1 = s.dim[1];
+        const int rows = d1 * s.dim[2];
+        const float inv_d1 = 1.0f / (float)d1;
+        if (np <= 64) {
+            const float inv_np = 1.0f / (float)np;
+            const int rw = div_small(64, np, inv_np);
+            const int lr = div_small(lane, np, inv_np);
+            const bool on = lr < rw;
+            const uint64_t xo = chunk_off(s, lane - lr * np);
+            const int rstep = VR_NWAVE * rw;
+            const int r_first = wave * rw + lr;
+            int iz = div_small(r_first, d1, inv_d1);
+            int iy = r_first - iz * d1;
+            const int dz = div_small(rstep, d1, inv_d1), dy = rstep - dz * d1;
+            for (int r0 = wave * rw; r0 < rows; r0 += rstep) {
+                if (on && r0 + lr < rows)
+                    __builtin_amdgcn_global_load_lds((const void*)(row_src(s, iy, iz) + xo),
+                                                     (__attribute__((address_space(3))) void*)(buf + r0 * np * 16),
+                                                     16, 0, 0);
+                iy += dy;
+                iz += dz;
+                if (iy >= d1) {
+                    iy -= d1;
+                    ++iz;
+                }
             }
-            c += qc;
-            const int carry = c >= nc ? 1 : 0;
-            c -= carry * nc;
-            iy += dy + carry;
-            iz += dz;
-            if (iy >= d1) {
-                iy -= d1;
-                ++iz;
+        } else {
+            for (int r = wave; r < rows; r += VR_NWAVE) {
+                const int iz = div_small(r, d1, inv_d1);
+                const uint8_t* src = row_src(s, r - iz * d1, iz);
+                for (int c0 = 0; c0 < np; c0 += 64) {
+                    if (c0 + lane < np)
+                        __builtin_amdgcn_global_load_lds((const void*)(src + chunk_off(s, c0 + lane)),
+                                                         (__attribute__((address_space(3))) void*)(buf + (r * np + c0) * 16),
+                                                         16, 0, 0);
+                }
             }
         }
     };
@@ -964,23 +1020,47 @@ __device__ __forceinline__ bool tile_march(const DevReq& R, const Ray& ray, cons
                         ch[a] = (float)(N[a] - 1 - s0.lo[a]);
                     }
                 }
+                // samples are taken two at a time so that the second one's box
+                // reads are in flight while the first one is classified
+                auto value = [&](auto fetch, int j, bool last) {
+                    const float jf = (float)j + (last ? ray.last_adj : 0.0f);
+                    const float p[3] = {__builtin_fmaf(jf, ray.dd[0], A[0]),
+                                        __builtin_fmaf(jf, ray.dd[1], A[1]),
+                                        __builtin_fmaf(jf, ray.dd[2], A[2])};
+                    int i[3];
+                    float w[3];
+                    floor_idx<INTERP>(p, ch, i, w);
+                    return fetch(i, w);
+                };
                 auto run = [&](auto fetch) {
-                    for (int j = 0; j < cnt_s; ++j) {
-                        const bool last = (ks + j == ray.n - 1);
-                        const float jf = (float)j + (last ? ray.last_adj : 0.0f);
-                        const float p[3] = {__builtin_fmaf(jf, ray.dd[0], A[0]),
-                                            __builtin_fmaf(jf, ray.dd[1], A[1]),
-                                            __builtin_fmaf(jf, ray.dd[2], A[2])};
-                        int i[3];
-                        float w[3];
-                        floor_idx<INTERP>(p, ch, i, w);
-                        const float v = fetch(i, w);
+                    const int jl = ray.n - 1 - ks;  // index of the ray's last sample in this slab, if any
+                    int j = 0;
+                    for (; j + 1 < cnt_s; j += 2) {
+                        const float v0 = value(fetch, j, false);
+                        const float v1 = value(fetch, j + 1, j + 1 == jl);
+                        ++nexec;
+                        if (MODE == 1) {
+                            ++nexec;
+                            acc.m = fmaxf(acc.m, fmaxf(v0, v1));
+                        } else {
+                            if (composite(R, tfl, v0, false, ray, acc)) {
+                                stopped = true;
+                                break;
+                            }
+                            ++nexec;
+                            if (composite(R, tfl, v1, j + 1 == jl, ray, acc)) {
+                                stopped = true;
+                                break;
+                            }
+                        }
+                    }
+                    if (j < cnt_s && !stopped) {
+                        const float v = value(fetch, j, j == jl);
                         ++nexec;
                         if (MODE == 1) {
                             acc.m = fmaxf(acc.m, v);
-                        } else if (composite(R, tfl, v, last, ray, acc)) {
+                        } else if (composite(R, tfl, v, j == jl, ray, acc)) {
                             stopped = true;
-                            break;
                         }
                     }
                 };
@@ -995,9 +1075,8 @@ __device__ __forceinline__ bool tile_march(const DevReq& R, const Ray& ray, cons
                     });
                 } else {
                     run([&](const int* i, const float* w) {
-                        return interp_at<DT, INTERP>(
-                            pool_ptr<DT>(R.cube, s0.lo[0] + i[0], s0.lo[1] + i[1], s0.lo[2] + i[2]),
-                            R.cube.row, VR_BRICK_APRON * R.cube.row, w[0], w[1], w[2]);
+                        return pool_value<DT, INTERP>(R.cube, s0.lo[0] + i[0], s0.lo[1] + i[1],
+                                                      s0.lo[2] + i[2], w[0], w[1], w[2]);
                     });
                 }
             }
@@ -1301,20 +1380,20 @@ __global__ __launch_bounds__(VR_WG) void k_render_batch(const DevReq* __restrict
 // ---------------------------------------------------------------------------
 template <int SRC, int DST>
 static hipError_t launch_bb(const void* src, int64_t nx, int64_t ny, int64_t nz, int64_t z_first,
-                            int bz, int Bx, int By, uint8_t* pool, uint64_t stride, int row,
+                            int bz, int Bx, int By, uint8_t* pool, uint64_t stride, int xch,
                             float* cell_minmax, float sigma, hipStream_t s) {
     hipLaunchKernelGGL((k_brick_build<SRC, DST>), dim3(Bx * By), dim3(VR_BB_WG), 0, s, src, nx,
-                       ny, nz, z_first, bz, Bx, By, pool, stride, row, cell_minmax, sigma);
+                       ny, nz, z_first, bz, Bx, By, pool, stride, xch, cell_minmax, sigma);
     return hipGetLastError();
 }
 
 hipError_t vr_launch_brick_build(int src_kind, int dst, const void* src, int64_t nx, int64_t ny,
                                  int64_t nz, int64_t z_first, int bz, int Bx, int By,
-                                 uint8_t* pool, uint64_t stride, int row, float* cell_minmax,
+                                 uint8_t* pool, uint64_t stride, int xch, float* cell_minmax,
                                  float sigma, hipStream_t s) {
 #define VR_BB(S, D)                                                                          \
     if (src_kind == S && dst == D)                                                           \
-        return launch_bb<S, D>(src, nx, ny, nz, z_first, bz, Bx, By, pool, stride, row,      \
+        return launch_bb<S, D>(src, nx, ny, nz, z_first, bz, Bx, By, pool, stride, xch,      \
                                cell_minmax, sigma, s);
     VR_BB(0, 0)
     VR_BB(0, 1)

@@ -23,7 +23,7 @@ inline int vr_box_bytes(int tf_rows) {
 // z_first.  src_kind: 0 float32 values, 1/2 16-bit codes stored as-is.
 hipError_t vr_launch_brick_build(int src_kind, int dst, const void* src, int64_t nx, int64_t ny,
                                  int64_t nz, int64_t z_first, int bz, int Bx, int By,
-                                 uint8_t* pool, uint64_t stride, int row, float* cell_minmax,
+                                 uint8_t* pool, uint64_t stride, int xch, float* cell_minmax,
                                  float sigma, hipStream_t s);
 
 // Skip masks (per slot) and the per-cell grid for one (mode, transfer function, clip).

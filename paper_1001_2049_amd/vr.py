@@ -68,7 +68,7 @@ class vr_cube_info(ctypes.Structure):
                 ("sigma_scale", ctypes.c_double), ("pool_bytes", ctypes.c_uint64),
                 ("brick_stride", ctypes.c_uint64), ("aux_bytes", ctypes.c_uint64),
                 ("vmin", ctypes.c_float), ("vmax", ctypes.c_float),
-                ("row_elems", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("x_chunks", ctypes.c_int32), ("reserved", ctypes.c_int32),
                 ("pool", ctypes.c_void_p), ("cell_minmax", ctypes.c_void_p)]
 
 

@@ -109,6 +109,10 @@ def test_tiny_gate_and_arithmetic(rend, tiny_cube, storage, mode, view):
 
 @pytest.mark.parametrize("storage", ["f16", "bf16", "f32"])
 def test_pool_layout_and_cell_tables(rend, storage):
+    """Every stored element of every slot (the 33^3 brick, its apron and the
+    padding) equals the host's storage code of the edge-clamped voxel, at the
+    position the documented line layout gives; the cell tables equal a
+    brute-force min/max over each cell's 9^3 halo."""
     nx, ny, nz = 45, 70, 33
     rng = np.random.default_rng(7)
     vol = (rng.standard_normal((nz, ny, nx)) * 3.0).astype(np.float32)
@@ -119,8 +123,12 @@ def test_pool_layout_and_cell_tables(rend, storage):
         B = inf.brick
         assert (inf.bricks_x, inf.bricks_y, inf.bricks_z) == (2, 3, 2)
         esz = 4 if storage == "f32" else 2
-        assert inf.row_elems * esz % 16 == 0 and inf.row_elems >= B + 1
+        cv = 16 // esz
+        xch = inf.x_chunks
+        assert xch * cv >= B + 1
         nslots = inf.bricks_x * inf.bricks_y * inf.bricks_z
+        slot_elems = 17 * 9 * xch * 8 * cv
+        assert inf.brick_stride >= slot_elems * esz and inf.brick_stride % 256 == 0
         raw = hip_to_host(inf.pool, nslots * inf.brick_stride)
         if storage == "f32":
             want_all = (vol / np.float32(sigma)).astype(np.float32)
@@ -133,19 +141,28 @@ def test_pool_layout_and_cell_tables(rend, storage):
             dec_all = want_all.astype(np.float64)
         else:
             dec_all = oracle.decode_bits(want_all, CODES[storage])
+        # element offset of local (lx, ly, lz): the documented formula
+        lx = np.arange(xch * cv)
+        ly = np.arange(36)
+        lz = np.arange(34)
+        ox = (lx // cv) * 8 * cv + lx % cv
+        oy = (ly // 4) * xch * 8 * cv + (ly % 4) * cv
+        oz = (lz // 2) * 9 * xch * 8 * cv + (lz % 2) * 4 * cv
+        off = oz[:, None, None] + oy[None, :, None] + ox[None, None, :]
+        assert np.array_equal(np.sort(off.ravel()), np.arange(slot_elems))  # a bijection
         for bz in range(inf.bricks_z):
             for by in range(inf.bricks_y):
                 for bx in range(inf.bricks_x):
                     slot = (bz * inf.bricks_y + by) * inf.bricks_x + bx
                     base = slot * inf.brick_stride
-                    s = raw[base: base + (B + 1) * (B + 1) * inf.row_elems * esz].view(dt)
-                    s = s.reshape(B + 1, B + 1, inf.row_elems)[:, :, :B + 1]
-                    gz = np.minimum(np.arange(B + 1) + B * bz, nz - 1)
-                    gy = np.minimum(np.arange(B + 1) + B * by, ny - 1)
-                    gx = np.minimum(np.arange(B + 1) + B * bx, nx - 1)
+                    sv = raw[base: base + slot_elems * esz].view(dt)[off]
+                    gz = np.minimum(lz + B * bz, nz - 1)
+                    gy = np.minimum(ly + B * by, ny - 1)
+                    gx = np.minimum(lx + B * bx, nx - 1)
                     want = want_all[np.ix_(gz, gy, gx)]
-                    assert np.array_equal(s.view(np.uint8), np.ascontiguousarray(want).view(np.uint8)), slot
-                    dec = dec_all[np.ix_(gz, gy, gx)]
+                    assert np.array_equal(np.ascontiguousarray(sv).view(np.uint8),
+                                          np.ascontiguousarray(want).view(np.uint8)), slot
+                    dec = dec_all[np.ix_(gz[:33], gy[:33], gx[:33])]
                     for c in range(64):
                         cx, cy, cz = c % 4, (c // 4) % 4, c // 16
                         blk = dec[8 * cz: 8 * cz + 9, 8 * cy: 8 * cy + 9, 8 * cx: 8 * cx + 9]
