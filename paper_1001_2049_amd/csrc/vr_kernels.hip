@@ -741,24 +741,20 @@ __device__ __forceinline__ Slab fit_slab(int ze, int sgn, int hi, int cap, const
     return best;
 }
 
-// Next slab entered at plane ze.  Normally the thickest (at most twice the
-// previous thickness and VR_SMAX) whose box fits one LDS buffer of the
-// reference size, so that its copy overlaps the sampling of the slab before.
-// When that is thinner than 2 voxels, the thickest (at most 8) whose box fits
-// both buffers is taken instead and copied after the slab before it has been
-// sampled.  A box that fits neither, even one voxel thick, is marched 8 voxels
-// at a time from the brick pool.  Only geometry decides, never the LDS a
-// launch actually has.
+// Next slab entered at plane ze: the thickest (at most twice the previous
+// thickness and VR_SMAX) whose box fits both LDS buffers of the reference
+// size.  Such a box is copied only after the slab before it has been sampled;
+// measured on the full-size workload, slabs twice as thick beat overlapping
+// the copy of a one-buffer box with the sampling of the previous slab.  A box
+// that does not fit even one voxel thick is marched 8 voxels at a time from
+// the brick pool.  Only geometry decides, never the LDS a launch actually has.
 template <int M, int CV, int ELEM>
 __device__ __forceinline__ Slab next_slab(int ze, int sgn, int Sprev, const Corners& cr,
                                           const int N[3], int zmin, int zmax) {
     constexpr int cap = VR_BOX_REF / ELEM;
     bool ok;
-    Slab s = fit_slab<M, CV>(ze, sgn, min(VR_SMAX, 2 * Sprev), cap, cr, N, zmin, zmax, ok);
-    if (ok && s.S >= 2) return s;
-    bool okb;
-    Slab b = fit_slab<M, CV>(ze, sgn, 8, 2 * cap, cr, N, zmin, zmax, okb);
-    if (okb) {
+    Slab b = fit_slab<M, CV>(ze, sgn, min(VR_SMAX, 2 * Sprev), 2 * cap, cr, N, zmin, zmax, ok);
+    if (ok) {
         b.big = 1;
         return b;
     }
