@@ -1415,10 +1415,20 @@ hipError_t vr_launch_classify(const float* cell_minmax, uint64_t* mask, uint32_t
     return hipGetLastError();
 }
 
+// Static plus dynamic LDS of a launch must fit the workgroup's 160 KB.
+static hipError_t check_lds(const void* kernel, size_t dynamic_bytes) {
+    hipFuncAttributes a;
+    hipError_t e = hipFuncGetAttributes(&a, kernel);
+    if (e != hipSuccess) return e;
+    return a.sharedSizeBytes + dynamic_bytes <= (size_t)VR_LDS_MAX ? hipSuccess : hipErrorInvalidValue;
+}
+
 template <int MODE, int DT, int INTERP>
 static hipError_t launch_r(const DevReq& R, const int* order, DevCounters* cnt, hipStream_t s) {
     const int grid = R.tiles_x * R.tiles_y;
     const size_t lds = (MODE == 0 ? (size_t)R.tf.n * 32 : 0) + 2 * (size_t)R.box_bytes;
+    const hipError_t e = check_lds((const void*)k_render<MODE, DT, INTERP>, lds);
+    if (e != hipSuccess) return e;
     hipLaunchKernelGGL((k_render<MODE, DT, INTERP>), dim3(grid), dim3(VR_WG), lds, s, R, order, cnt);
     return hipGetLastError();
 }
@@ -1453,6 +1463,8 @@ hipError_t vr_launch_render(const DevReq& R, int* order, unsigned* hist, DevCoun
 hipError_t vr_launch_batch(const DevReq* reqs, const DevItem* items, const int* nitems,
                            int items_cap, DevItem* sorted, unsigned* hist, unsigned* head,
                            DevCounters* cnt, size_t lds_bytes, int grid, hipStream_t s) {
+    const hipError_t le = check_lds((const void*)k_render_batch, lds_bytes);
+    if (le != hipSuccess) return le;
     const int ob = (items_cap + 255) / 256;
     hipLaunchKernelGGL(k_order_clear, dim3(1), dim3(2 * VR_NBUCKET), 0, s, hist);
     hipLaunchKernelGGL(k_order_count_batch, dim3(ob), dim3(256), 0, s, reqs, items, nitems, hist);

@@ -303,3 +303,23 @@ def test_batch_with_many_fresh_skip_masks(R, tiny, tiny_cube):
             singles.append(to_np(R.render(tiny_cube, 96, 80, mode=mode)).copy())
     for a, b in zip(got, singles):
         assert np.array_equal(a.view(np.uint32), b.view(np.uint32))
+
+
+def test_large_transfer_function_parity(R, tiny, tiny_cube):
+    """A 4096-row transfer function leaves little LDS for slab boxes, so most
+    slabs are sampled straight from the brick pool; the image still matches
+    the reference, and equals the image a batch launch renders."""
+    import torch
+    wl, vol, _ = tiny
+    tf = synth.ramp_tf(4096, wl.kappa_max)
+    cam = synth.orbit_camera(64, 64, 128, 0.4, 0.3)
+    R.set_transfer_function(tf, wl.v0, wl.v1)
+    R.set_noise_clip(wl.clip_k, 1.0)
+    R.set_camera(cam)
+    img = to_np(R.render(tiny_cube, 160, 120, mode="ea"))
+    ref = ref_render(vol, wl_kwargs(wl, tf), cam, 160, 120, "ea", "trilinear")
+    compare_ea(img, ref["image"], TOL_F32, ref["flags"])
+    out = R.output(160, 120, "ea")
+    R.render_batch([R.request(tiny_cube, cam, 160, 120, out, mode="ea", clip=wl.clip_k)])
+    torch.cuda.synchronize()
+    assert np.array_equal(img.view(np.uint32), to_np(out).view(np.uint32))
