@@ -131,6 +131,9 @@ def lib():
         if not os.path.exists(LIB_PATH):
             raise RuntimeError("libvr.so is not built: run paper_1001_2049_amd/build.py "
                                "(or __graft_entry__.build()) first")
+        # PyTorch owns device memory and streams: its HIP runtime must be the one
+        # this library binds to (same soname), so it is loaded first
+        import torch  # noqa: F401
         L = ctypes.CDLL(LIB_PATH)
         for name, (res, args) in _SIGNATURES.items():
             fn = getattr(L, name)

@@ -154,6 +154,125 @@ def cube(spec: CubeSpec, threads: int | None = None) -> np.ndarray:
 
 
 # ----------------------------------------------------------------------------
+# The same generator evaluated on the GPU (for cubes too large to generate on
+# the host in reasonable time).  Source factors are tabulated here with the C
+# library's exp, in the operation order of synth.c, so source terms match the
+# CPU generator bit for bit; see synth_gpu.hip for the noise.
+# ----------------------------------------------------------------------------
+_GPU_SRC = os.path.join(_HERE, "synth_gpu.hip")
+_GPU_LIB_PATH = os.path.join(_HERE, "libsynth_gpu.so")
+_gpu_lib = None
+
+
+def build_gpu(force: bool = True) -> str:
+    """Compile synth_gpu.hip into libsynth_gpu.so (hipcc, gfx950)."""
+    if force or not os.path.exists(_GPU_LIB_PATH):
+        tmp = _GPU_LIB_PATH + ".tmp%d" % os.getpid()
+        subprocess.check_call(["/opt/rocm/bin/hipcc", "--offload-arch=gfx950", "-O3", "-fPIC", "-shared",
+                               "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+                               "-o", tmp, _GPU_SRC])
+        os.replace(tmp, _GPU_LIB_PATH)
+    return _GPU_LIB_PATH
+
+
+def gpu_lib():
+    global _gpu_lib
+    if _gpu_lib is None:
+        if not os.path.exists(_GPU_LIB_PATH):
+            raise RuntimeError("libsynth_gpu.so is not built (synth.build_gpu())")
+        # PyTorch's HIP runtime must be the one in the process before this
+        # library resolves its own runtime dependency to the same soname
+        import torch  # noqa: F401
+        L = ctypes.CDLL(_GPU_LIB_PATH)
+        vp, i64 = ctypes.c_void_p, ctypes.c_int64
+        L.synth_gpu_planes.argtypes = [ctypes.c_uint64, i64, i64, ctypes.c_double, ctypes.c_int, i64, i64,
+                                       vp, vp, vp, vp, vp, vp, vp, vp, vp, ctypes.c_int, vp]
+        L.synth_gpu_planes.restype = ctypes.c_int
+        _gpu_lib = L
+    return _gpu_lib
+
+
+def source_tables(spec: CubeSpec, src: np.ndarray):
+    """Per-source rectangles and x / y factor tables, as synth.c evaluates them."""
+    nx, ny = spec.nx, spec.ny
+    rect = np.zeros((len(src), 4), dtype=np.int32)
+    fx_off = np.zeros(len(src), dtype=np.int64)
+    fy_off = np.zeros(len(src), dtype=np.int64)
+    fx, fy, live = [], [], np.zeros(len(src), dtype=bool)
+    for s, (x0, y0, zc, A, ss, sz) in enumerate(src.tolist()):
+        xa = max(int(math.ceil(x0 - 5.0 * ss)), 0)
+        xb = min(int(math.floor(x0 + 5.0 * ss)), nx - 1)
+        ya = max(int(math.ceil(y0 - 5.0 * ss)), 0)
+        yb = min(int(math.floor(y0 + 5.0 * ss)), ny - 1)
+        if xa > xb or ya > yb:
+            continue
+        live[s] = True
+        rect[s] = (xa, xb, ya, yb)
+        fx_off[s] = len(fx)
+        for x in range(xa, xb + 1):
+            dx = float(x) - x0
+            fx.append(math.exp(-0.5 * dx * dx / (ss * ss)))
+        fy_off[s] = len(fy)
+        for y in range(ya, yb + 1):
+            dy = float(y) - y0
+            fy.append(math.exp(-0.5 * dy * dy / (ss * ss)))
+    return rect, fx_off, fy_off, np.asarray(fx or [0.0]), np.asarray(fy or [0.0]), live
+
+
+def plane_entries(spec: CubeSpec, src: np.ndarray, live: np.ndarray, z0: int, nzs: int):
+    """For planes z0 .. z0+nzs-1: CSR offsets, source indices (catalogue order)
+    and factors A * sigma * exp(-dz^2 / (2 sz^2)) of the sources that reach them."""
+    zs, ss_, aa = [], [], []
+    for s, (x0, y0, zc, A, ssp, sz) in enumerate(src.tolist()):
+        if not live[s]:
+            continue
+        lo = max(int(math.floor(zc - 5.0 * sz)) - 1, z0)
+        hi = min(int(math.ceil(zc + 5.0 * sz)) + 1, z0 + nzs - 1)
+        for z in range(lo, hi + 1):
+            dz = float(z) - zc
+            if abs(dz) > 5.0 * sz:
+                continue
+            zs.append(z - z0)
+            ss_.append(s)
+            aa.append(A * spec.sigma * math.exp(-0.5 * dz * dz / (sz * sz)))
+    zs = np.asarray(zs, dtype=np.int64)
+    ss_ = np.asarray(ss_, dtype=np.int32)
+    aa = np.asarray(aa, dtype=np.float64)
+    order = np.lexsort((ss_, zs))
+    zs, ss_, aa = zs[order], ss_[order], aa[order]
+    off = np.zeros(nzs + 1, dtype=np.int64)
+    np.add.at(off, zs + 1, 1)
+    off = np.cumsum(off)
+    return off, (ss_ if len(ss_) else np.zeros(1, np.int32)), (aa if len(aa) else np.zeros(1))
+
+
+def cube_gpu(spec: CubeSpec, out, chunk: int = 64) -> None:
+    """Fill `out` (a contiguous float32 CUDA tensor of shape (nz, ny, nx)) with the cube."""
+    import torch
+    assert out.is_cuda and out.dtype == torch.float32 and out.is_contiguous()
+    assert tuple(out.shape) == (spec.nz, spec.ny, spec.nx)
+    dev = out.device
+    src = source_catalogue(spec)
+    rect, fx_off, fy_off, fx, fy, live = source_tables(spec, src)
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+    d_rect, d_fxo, d_fyo, d_fx, d_fy = t(rect.reshape(-1) if len(rect) else np.zeros(4, np.int32)), \
+        t(fx_off if len(fx_off) else np.zeros(1, np.int64)), t(fy_off if len(fy_off) else np.zeros(1, np.int64)), t(fx), t(fy)
+    stream = torch.cuda.current_stream(dev).cuda_stream
+    for z0 in range(0, spec.nz, chunk):
+        nzs = min(chunk, spec.nz - z0)
+        off, ents, aa = plane_entries(spec, src, live, z0, nzs)
+        d_off, d_ent, d_a = t(off), t(ents), t(aa)
+        rc = gpu_lib().synth_gpu_planes(spec.seed, spec.nx, spec.ny, spec.sigma, int(spec.noise), z0, nzs,
+                                        d_off.data_ptr(), d_ent.data_ptr(), d_a.data_ptr(),
+                                        d_rect.data_ptr(), d_fxo.data_ptr(), d_fyo.data_ptr(),
+                                        d_fx.data_ptr(), d_fy.data_ptr(), out[z0].data_ptr(),
+                                        dev.index if dev.index is not None else 0, stream)
+        if rc != 0:
+            raise RuntimeError("synth_gpu_planes failed (%d)" % rc)
+    torch.cuda.synchronize(dev)
+
+
+# ----------------------------------------------------------------------------
 # Transfer functions (tables are inputs)
 # ----------------------------------------------------------------------------
 def ramp_tf(n: int = 256, kappa_max: float = 1.0) -> np.ndarray:

@@ -1,0 +1,87 @@
+"""The large workload: a 2048 x 2048 x 4096 cube (noise plus 5000 sources)
+stored as FP16, a 2048 x 2048 perspective view with the transfer function
+clipped at 4 sigma (most cells are empty and skipped), and a 64-view orbit
+rendered in one batched launch.
+
+The cube is generated on the GPU with the seeded generator (synth), rounded
+to FP16 codes (round to nearest even) and copied to the host for the
+reference, which reads exactly those codes; the renderer uploads the same
+float32 values and rounds them itself.  Sampled pixels are compared with the
+FP64 reference at the float32 tolerance (arithmetic check on decoded values),
+and batch members with their single renders bit for bit."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from gpu_common import TOL_F32, compare_ea, compare_mip, ref_render, wl_kwargs
+
+pytestmark = pytest.mark.gpu
+
+
+def orbit64(spec, i, W):
+    return synth.orbit_camera(spec.nx, spec.ny, spec.nz, 2.0 * math.pi * i / 64, math.radians(20.0))
+
+
+@pytest.fixture(scope="module")
+def large():
+    import torch
+    from paper_1001_2049_amd import Renderer
+    synth.gpu_lib()  # built by __graft_entry__.build()
+    wl = synth.large()
+    spec = wl.cube
+    vals = torch.empty((spec.nz, spec.ny, spec.nx), dtype=torch.float32, device="cuda")
+    synth.cube_gpu(spec, vals)
+    r = Renderer(0)
+    cube = r.upload(vals, "f16")
+    codes = np.empty((spec.nz, spec.ny, spec.nx), dtype=np.uint16)
+    for z0 in range(0, spec.nz, 256):
+        codes[z0:z0 + 256] = vals[z0:z0 + 256].half().cpu().numpy().view(np.uint16)
+    del vals
+    torch.cuda.empty_cache()
+    tf = synth.ramp_tf(256, wl.kappa_max)
+    r.set_transfer_function(tf, wl.v0, wl.v1)
+    r.set_noise_clip(wl.clip_k, 1.0)
+    yield wl, r, cube, codes, tf
+    r.close()
+    torch.cuda.empty_cache()
+
+
+@pytest.mark.parametrize("mode", ["ea", "mip"])
+def test_large_cube_sampled_pixels(large, mode):
+    import torch
+    wl, r, cube, codes, tf = large
+    W = H = wl.width
+    cam = orbit64(wl.cube, 0, W)
+    r.set_camera(cam)
+    img, st = r.render(cube, W, H, mode=mode, stats=True)
+    torch.cuda.synchronize()
+    got_img = img.cpu().numpy()
+    px = synth.pixel_subset(777, W, H, 300)
+    got = got_img[px[:, 1], px[:, 0]]
+    ref = ref_render(codes, wl_kwargs(wl, tf), cam, W, H, mode, "trilinear", pixels=px,
+                     vox_dtype=oracle.F16)
+    if mode == "ea":
+        info = compare_ea(got, ref["values"], TOL_F32, ref["flags"])
+    else:
+        info = compare_mip(got, ref["values"], TOL_F32, ref["flags"])
+    print("large %s %s stats=%s" % (mode, info, st))
+    assert st["cells_skipped"] > 0 and st["samples_exec"] < st["samples_nominal"]
+
+
+def test_large_orbit_batch_equals_single(large):
+    import torch
+    wl, r, cube, codes, tf = large
+    W = H = wl.width
+    outs = [r.output(W, H, "ea") for _ in range(64)]
+    reqs = [r.request(cube, orbit64(wl.cube, i, W), W, H, outs[i], mode="ea", clip=wl.clip_k)
+            for i in range(64)]
+    r.render_batch(reqs)
+    torch.cuda.synchronize()
+    for i in (0, 21, 63):
+        r.set_camera(orbit64(wl.cube, i, W))
+        single = r.render(cube, W, H, mode="ea")
+        torch.cuda.synchronize()
+        assert torch.equal(single.view(torch.int32), outs[i].view(torch.int32)), i
