@@ -434,6 +434,43 @@ __device__ __forceinline__ bool composite(const DevReq& R, const float* __restri
     return acc.T <= R.ert_T;
 }
 
+// Two consecutive samples of one ray, composited as composite() would one
+// after the other, without a branch between them: once the first makes the
+// ray opaque enough to stop, the second enters with opacity factor 1 and
+// weight 0, which leaves colour and transmittance exactly as they were.
+// nexec counts the samples composited; returns true when the ray stops.
+__device__ __forceinline__ bool composite2(const DevReq& R, const float* __restrict__ tfl, float v0,
+                                           float v1, bool last1, const Ray& ray, Accum& acc,
+                                           unsigned& nexec) {
+    const float hi = (float)(R.tf.n - 1);
+    const float u0 = __builtin_amdgcn_fmed3f(__builtin_fmaf(v0, R.tf.scale, R.tf.bias), 0.0f, hi);
+    const float u1 = __builtin_amdgcn_fmed3f(__builtin_fmaf(v1, R.tf.scale, R.tf.bias), 0.0f, hi);
+    const float g0 = __builtin_amdgcn_fractf(u0), g1 = __builtin_amdgcn_fractf(u1);
+    const float4* ra = (const float4*)(tfl + 8 * (int)u0);
+    const float4* rb = (const float4*)(tfl + 8 * (int)u1);
+    const float4 a0 = ra[0], da = ra[1], b0 = rb[0], db = rb[1];
+    float k0 = __builtin_fmaf(g0, da.w, a0.w);
+    float k1 = __builtin_fmaf(g1, db.w, b0.w);
+    k0 = v0 < R.tf.clip ? 0.0f : k0;
+    k1 = v1 < R.tf.clip ? 0.0f : k1;
+    const float e0 = __builtin_amdgcn_exp2f(k0 * ray.c_full);
+    const float e1r = __builtin_amdgcn_exp2f(k1 * (last1 ? ray.c_last : ray.c_full));
+    const float w0 = acc.T * (1.0f - e0);
+    acc.C0 = __builtin_fmaf(w0, __builtin_fmaf(g0, da.x, a0.x), acc.C0);
+    acc.C1 = __builtin_fmaf(w0, __builtin_fmaf(g0, da.y, a0.y), acc.C1);
+    acc.C2 = __builtin_fmaf(w0, __builtin_fmaf(g0, da.z, a0.z), acc.C2);
+    const float T0 = acc.T * e0;
+    const bool go = T0 > R.ert_T;
+    const float e1 = go ? e1r : 1.0f;
+    const float w1 = T0 * (1.0f - e1);
+    acc.C0 = __builtin_fmaf(w1, __builtin_fmaf(g1, db.x, b0.x), acc.C0);
+    acc.C1 = __builtin_fmaf(w1, __builtin_fmaf(g1, db.y, b0.y), acc.C1);
+    acc.C2 = __builtin_fmaf(w1, __builtin_fmaf(g1, db.z, b0.z), acc.C2);
+    acc.T = T0 * e1;
+    nexec += go ? 2u : 1u;
+    return acc.T <= R.ert_T;
+}
+
 template <int MODE>
 __device__ __forceinline__ void store_pixel(const DevReq& R, int px, int py, bool hit,
                                             const Accum& acc) {
@@ -663,11 +700,21 @@ struct Slab {
                   // previous slab takes both buffers)
 };
 
+template <bool B>
+struct BoolC {
+    static constexpr bool value = B;
+};
+
+// skip-grid rows of a slab box kept in LDS for the waves' own checks
+#define VR_CROW 128
+
 struct TileShared {
-    int red[4];    // tile-start reductions: first/last sample planes
-    int any[8];    // slab k may contribute (skip grid), ring by k % 8
-    int alive[3];  // some ray still marching after slab k, ring by k % 3
-    Slab ring[4];  // slab k's geometry, ring by k % 4 (S == 0: no such slab)
+    int red[4];         // tile-start reductions: first/last sample planes
+    int any[8];         // slab k may contribute (skip grid), ring by k % 8
+    unsigned nact[8];   // active cells of slab k's box (2^20 and up: rows not kept), ring by k % 8
+    int alive[3];       // some ray still marching after slab k, ring by k % 3
+    Slab ring[4];       // slab k's geometry, ring by k % 4 (S == 0: no such slab)
+    uint64_t crow[3][VR_CROW];  // slab k's cell rows (bit i: cell c0x + i), ring by k % 3
 };
 
 template <int M, int CV>
@@ -864,13 +911,20 @@ __device__ __forceinline__ bool tile_march(const DevReq& R, const Ray& ray, cons
         const float kf = ceilf((((float)zx - om) * inv_dm - tinf) * inv_step - 0.5f);
         return kf < (float)kprev ? kprev : (kf > (float)ray.n ? ray.n : (int)kf);
     };
-    // skip-grid words of a slab's cells: issue the loads (one cell row per thread)
+    // Skip-grid words of a slab's cells: bits_issue loads them (one row of cells
+    // along x per thread); bits_done, once they have landed, marks the slab as
+    // possibly contributing and keeps rows of up to 64 cells in LDS (slabs of at
+    // most VR_CROW rows) for the finer per-wave checks during sampling.
     const int Cx = 4 * R.cube.bx, Cy = 4 * R.cube.by;
-    auto bits_issue = [&](const Slab& s, uint32_t& w0w, uint32_t& w1w, uint32_t& m0, uint32_t& m1,
-                          bool& wide) {
-        w0w = w1w = m0 = m1 = 0u;
-        wide = false;
-        if (s.S == 0 || s.elems == 0) return;
+    struct Bits {
+        uint32_t w0, w1, m0, m1;
+        int lob, row;  // first bit in word w0; LDS row this thread keeps (-1: none)
+        int wide;      // treated as active; the slab's rows are not kept
+        int nofine;    // the slab's rows are not kept
+    };
+    auto bits_issue = [&](const Slab& s) -> Bits {
+        Bits b = {0u, 0u, 0u, 0u, 0, -1, 0, 0};
+        if (s.S == 0 || s.elems == 0) return b;
         int c0[3], c1[3];
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
@@ -879,28 +933,43 @@ __device__ __forceinline__ bool tile_march(const DevReq& R, const Ray& ray, cons
         }
         const int ny_ = c1[1] - c0[1] + 1, nrow = ny_ * (c1[2] - c0[2] + 1);
         if (nrow > VR_WG) {
-            wide = tid == 0;  // more cell rows than threads: treated as active
-            return;
+            b.wide = tid == 0;  // more cell rows than threads: treated as active
+            return b;
         }
-        if (tid >= nrow) return;
+        b.nofine = (tid == 0 && nrow > VR_CROW) ? 1 : 0;
+        if (tid >= nrow) return b;
         const int czr = div_small(tid, ny_, 1.0f / (float)ny_);
         const int cy = c0[1] + tid - czr * ny_, cz = c0[2] + czr;
         const int64_t b0 = ((int64_t)cz * Cy + cy) * Cx + c0[0];
         const int64_t b1 = b0 + (c1[0] - c0[0]);
         const int64_t wa = b0 >> 5, wb = b1 >> 5;
         if (wb - wa > 1) {
-            wide = true;  // more than two words: treated as active
-            return;
+            b.wide = 1;  // more than two words: treated as active
+            return b;
         }
         const uint32_t lo_bit = (uint32_t)(b0 & 31), hi_bit = (uint32_t)(b1 & 31);
         if (wa == wb) {
-            m0 = (hi_bit == 31 ? 0xffffffffu : ((1u << (hi_bit + 1)) - 1u)) & ~((1u << lo_bit) - 1u);
+            b.m0 = (hi_bit == 31 ? 0xffffffffu : ((1u << (hi_bit + 1)) - 1u)) & ~((1u << lo_bit) - 1u);
         } else {
-            m0 = ~((1u << lo_bit) - 1u);
-            m1 = hi_bit == 31 ? 0xffffffffu : ((1u << (hi_bit + 1)) - 1u);
-            w1w = R.cube.cellbits[wb];
+            b.m0 = ~((1u << lo_bit) - 1u);
+            b.m1 = hi_bit == 31 ? 0xffffffffu : ((1u << (hi_bit + 1)) - 1u);
+            b.w1 = R.cube.cellbits[wb];
         }
-        w0w = R.cube.cellbits[wa];
+        b.w0 = R.cube.cellbits[wa];
+        b.lob = (int)lo_bit;
+        b.row = nrow <= VR_CROW ? tid : -1;
+        return b;
+    };
+    auto bits_done = [&](int k, const Bits& b) {
+        const uint32_t lo = b.w0 & b.m0, hi = b.w1 & b.m1;
+        if (b.wide || lo || hi) sh.any[k & 7] = 1;
+        unsigned add = (b.wide || b.nofine) ? (1u << 20) : 0u;
+        if (b.row >= 0) {
+            const uint64_t r = ((((uint64_t)hi) << 32) | lo) >> b.lob;
+            sh.crow[k % 3][b.row] = r;
+            add += (unsigned)__popcll(r);
+        }
+        if (add) atomicAdd(&sh.nact[k & 7], add);
     };
     // Copy a slab's box into its LDS buffer: the box is row-major over
     // [z][y][16-byte chunk] with np chunks per row, and global->LDS loads write
@@ -973,12 +1042,8 @@ __device__ __forceinline__ bool tile_march(const DevReq& R, const Ray& ray, cons
     Slab s0 = sh.ring[0], s1 = sh.ring[1];
     int ks = 0, ke0 = slab_end(s0, 0);
     if (R.use_skip) {
-        uint32_t w0w, w1w, m0, m1;
-        bool wide;
-        bits_issue(s0, w0w, w1w, m0, m1, wide);
-        if (wide || (w0w & m0) || (w1w & m1)) sh.any[0] = 1;
-        bits_issue(s1, w0w, w1w, m0, m1, wide);
-        if (wide || (w0w & m0) || (w1w & m1)) sh.any[1] = 1;
+        bits_done(0, bits_issue(s0));
+        bits_done(1, bits_issue(s1));
         __syncthreads();
     }
     if (sh.any[0]) box_dma(s0);
@@ -988,15 +1053,15 @@ __device__ __forceinline__ bool tile_march(const DevReq& R, const Ray& ray, cons
         if (wave == 0) produce((it + 2) & 3);
         if (tid == 0) {
             sh.any[(it + 3) & 7] = R.use_skip ? 0 : 1;
+            sh.nact[(it + 3) & 7] = 0u;
             sh.alive[it % 3] = 0;
         }
         __builtin_amdgcn_s_waitcnt(0);  // own box copies of slab it have landed
         __syncthreads();
         if (it > 0 && sh.alive[(it - 1) % 3] == 0) break;
         const Slab s2 = sh.ring[(it + 2) & 3];
-        uint32_t bw0 = 0, bw1 = 0, bm0 = 0, bm1 = 0;
-        bool bwide = false;
-        if (R.use_skip) bits_issue(s2, bw0, bw1, bm0, bm1, bwide);
+        Bits bb = {0u, 0u, 0u, 0u, 0, -1, 0, 0};
+        if (R.use_skip) bb = bits_issue(s2);
         if (!s1.late && sh.any[(it + 1) & 7]) box_dma(s1);
         const int ke1 = slab_end(s1, ke0);
         // ---- sample slab it
@@ -1028,26 +1093,59 @@ __device__ __forceinline__ bool tile_march(const DevReq& R, const Ray& ray, cons
                     floor_idx<INTERP>(p, ch, i, w);
                     return fetch(i, w);
                 };
-                auto run = [&](auto fetch) {
+                // Finer skip where under a quarter of the box's cells are
+                // active: before every 8 samples each lane bounds the cells
+                // its samples j .. j+7 can touch (positions at j - 1/2, the
+                // last sample's earliest, and j + 7: per axis the clamped
+                // index is monotone in the position), and the wave passes
+                // over the 8 samples when no lane touches an active cell.
+                int cb0[3], cb1[3];
+#pragma unroll
+                for (int a = 0; a < 3; ++a) {
+                    cb0[a] = s0.lo[a] >> 3;
+                    cb1[a] = (s0.lo[a] + s0.dim[a] - 2) >> 3;
+                }
+                const int nyc = cb1[1] - cb0[1] + 1;
+                const unsigned ncell = (unsigned)((cb1[0] - cb0[0] + 1) * nyc * (cb1[2] - cb0[2] + 1));
+                const bool fine = R.use_skip && 4u * (unsigned)__builtin_amdgcn_readfirstlane((int)sh.nact[it & 7]) <= ncell;
+                const uint64_t* crow = sh.crow[it % 3];
+                auto live = [&](int j) -> bool {
+                    const float ja = (float)j - 0.5f, jb = (float)j + 7.0f;
+                    int c_lo[3], c_hi[3];
+#pragma unroll
+                    for (int a = 0; a < 3; ++a) {
+                        const float qa = __builtin_amdgcn_fmed3f(__builtin_fmaf(ja, ray.dd[a], A[a]), 0.0f, ch[a]);
+                        const float qb = __builtin_amdgcn_fmed3f(__builtin_fmaf(jb, ray.dd[a], A[a]), 0.0f, ch[a]);
+                        const int ia = INTERP == 1 ? (int)qa : (int)(qa + 0.5f);
+                        const int ib = INTERP == 1 ? (int)qb : (int)(qb + 0.5f);
+                        c_lo[a] = min(max((s0.lo[a] + min(ia, ib)) >> 3, cb0[a]), cb1[a]);
+                        c_hi[a] = min(max((s0.lo[a] + max(ia, ib)) >> 3, cb0[a]), cb1[a]);
+                    }
+                    const int nbx = c_hi[0] - c_lo[0] + 1;
+                    const uint64_t xm = (nbx >= 64 ? ~0ull : ((1ull << nbx) - 1ull)) << (c_lo[0] - cb0[0]);
+                    uint64_t hit = 0;
+                    for (int cz = c_lo[2]; cz <= c_hi[2]; ++cz)
+                        for (int cy = c_lo[1]; cy <= c_hi[1]; ++cy)
+                            hit |= crow[(cz - cb0[2]) * nyc + (cy - cb0[1])];
+                    return (hit & xm) != 0ull;
+                };
+                auto run = [&](auto fetch, auto chunked) {
                     const int jl = ray.n - 1 - ks;  // index of the ray's last sample in this slab, if any
                     int j = 0;
                     for (; j + 1 < cnt_s; j += 2) {
+                        if (decltype(chunked)::value && (j & 7) == 0 && __ballot(live(j)) == 0ull) {
+                            nskip += (unsigned)min(8, cnt_s - j);
+                            j += 6;
+                            continue;
+                        }
                         const float v0 = value(fetch, j, false);
                         const float v1 = value(fetch, j + 1, j + 1 == jl);
-                        ++nexec;
                         if (MODE == 1) {
-                            ++nexec;
+                            nexec += 2;
                             acc.m = fmaxf(acc.m, fmaxf(v0, v1));
-                        } else {
-                            if (composite(R, tfl, v0, false, ray, acc)) {
-                                stopped = true;
-                                break;
-                            }
-                            ++nexec;
-                            if (composite(R, tfl, v1, j + 1 == jl, ray, acc)) {
-                                stopped = true;
-                                break;
-                            }
+                        } else if (composite2(R, tfl, v0, v1, j + 1 == jl, ray, acc, nexec)) {
+                            stopped = true;
+                            break;
                         }
                     }
                     if (j < cnt_s && !stopped) {
@@ -1065,19 +1163,27 @@ __device__ __forceinline__ bool tile_march(const DevReq& R, const Ray& ray, cons
                     const int pitch = s0.np * CV;
                     const int sy = pitch, sz = pitch * s0.dim[1];
                     const int xoff = s0.lo[0] - s0.xa;
-                    run([&](const int* i, const float* w) {
+                    auto fetch = [&](const int* i, const float* w) {
                         const int idx = (int)__umul24(__umul24(i[2], s0.dim[1]) + i[1], pitch) + i[0] + xoff;
                         return interp_box<DT, INTERP>(box, idx, sy, sz, w[0], w[1], w[2]);
-                    });
+                    };
+                    if (fine)
+                        run(fetch, BoolC<true>());
+                    else
+                        run(fetch, BoolC<false>());
                 } else {
-                    run([&](const int* i, const float* w) {
+                    auto fetch = [&](const int* i, const float* w) {
                         return pool_value<DT, INTERP>(R.cube, s0.lo[0] + i[0], s0.lo[1] + i[1],
                                                       s0.lo[2] + i[2], w[0], w[1], w[2]);
-                    });
+                    };
+                    if (fine)
+                        run(fetch, BoolC<true>());
+                    else
+                        run(fetch, BoolC<false>());
                 }
             }
         }
-        if (R.use_skip && (bwide || (bw0 & bm0) || (bw1 & bm1))) sh.any[(it + 2) & 7] = 1;
+        if (R.use_skip) bits_done(it + 2, bb);
         const bool done = !act || stopped || ke0 >= ray.n;
         if (__ballot(!done) != 0ull && lane == 0) sh.alive[it % 3] = 1;
         if (s1.late) {  // the box of slab it + 1 needs the LDS slab it used
@@ -1116,7 +1222,10 @@ __device__ __forceinline__ bool render_tile(const DevReq& R, const int tx, const
     if (tid == 0) {
         sh.red[0] = VR_BIG;
         sh.red[1] = -VR_BIG;
-        for (int q = 0; q < 8; ++q) sh.any[q] = R.use_skip ? 0 : 1;
+        for (int q = 0; q < 8; ++q) {
+            sh.any[q] = R.use_skip ? 0 : 1;
+            sh.nact[q] = 0u;
+        }
         sh.alive[0] = sh.alive[1] = sh.alive[2] = 0;
     }
     // tile centre ray fixes the major axis; the corner rays bound the tile's rays
