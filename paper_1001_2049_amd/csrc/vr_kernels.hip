@@ -415,6 +415,7 @@ struct Accum {
 // the ray becomes opaque enough to stop.
 __device__ __forceinline__ bool composite(const DevReq& R, const float* __restrict__ tfl, float v,
                                           bool last, const Ray& ray, Accum& acc) {
+    if (v < R.tf.clip) return false;  // opacity factor 1, weight 0: no change
     float u = __builtin_fmaf(v, R.tf.scale, R.tf.bias);
     u = __builtin_amdgcn_fmed3f(u, 0.0f, (float)(R.tf.n - 1));
     // u >= 0: truncation is the floor; at u = n - 1 the last row is taken with
@@ -442,6 +443,12 @@ __device__ __forceinline__ bool composite(const DevReq& R, const float* __restri
 __device__ __forceinline__ bool composite2(const DevReq& R, const float* __restrict__ tfl, float v0,
                                            float v1, bool last1, const Ray& ray, Accum& acc,
                                            unsigned& nexec) {
+    // Below the clip a sample has opacity factor exactly 1 and weight 0 and
+    // changes nothing: the table rows are read only for lanes that need them.
+    if (v0 < R.tf.clip && v1 < R.tf.clip) {
+        nexec += 2u;
+        return false;
+    }
     const float hi = (float)(R.tf.n - 1);
     const float u0 = __builtin_amdgcn_fmed3f(__builtin_fmaf(v0, R.tf.scale, R.tf.bias), 0.0f, hi);
     const float u1 = __builtin_amdgcn_fmed3f(__builtin_fmaf(v1, R.tf.scale, R.tf.bias), 0.0f, hi);

@@ -279,6 +279,35 @@ def test_full_cube_sampled_pixels(R, full_workload, mode):
         R.release(cube)
 
 
+@pytest.mark.parametrize("storage", ["f32", "f16"])
+def test_full_cube_wave_skip_is_bit_invisible(R, full_workload, storage):
+    """Full-size cube with the transfer function and clip raised to 4 and 5
+    sigma, where under a quarter of most slab boxes' cells are active and the
+    waves pass over chunks of 8 samples: images with and without skipping are
+    bit-identical (EA and MIP, trilinear and nearest, four orbit views), and
+    skipping removes most samples."""
+    import torch
+    wl, vol, tf = full_workload
+    cube = R.upload(vol, storage)
+    try:
+        for clip in (4.0, 5.0):
+            R.set_transfer_function(tf, clip, wl.v1)
+            R.set_noise_clip(clip, 1.0)
+            for vi, (th, ph) in enumerate(synth.orbit_angles(77, 4)):
+                R.set_camera(synth.orbit_camera(512, 512, 1024, th, ph))
+                for mode, interp in (("ea", "trilinear"), ("mip", "trilinear"), ("mip", "nearest")):
+                    a, sa = R.render(cube, 768, 640, mode=mode, interp=interp, use_skip=True, stats=True)
+                    b, sb = R.render(cube, 768, 640, mode=mode, interp=interp, use_skip=False, stats=True)
+                    torch.cuda.synchronize()
+                    assert torch.equal(a.view(torch.int32), b.view(torch.int32)), (clip, vi, mode, interp)
+                    assert sa["samples_nominal"] == sb["samples_nominal"]
+                    print("wave skip %s clip %.0f view%d %s/%s: exec %d of %d" % (
+                        storage, clip, vi, mode, interp, sa["samples_exec"], sb["samples_exec"]))
+                    assert sa["samples_exec"] < 0.75 * sb["samples_exec"], (clip, vi, mode, interp)
+    finally:
+        R.release(cube)
+
+
 def test_batch_with_many_fresh_skip_masks(R, tiny, tiny_cube):
     """One batch whose requests need more skip masks on one cube than the cache
     holds (EA and MIP, ten noise clips): every image equals its single render."""
