@@ -352,17 +352,6 @@ __device__ __forceinline__ float trilerp(float c000, float c100, float c010, flo
     return __builtin_fmaf(w2, y1 - y0, y0);
 }
 
-// Value at a corner-0 pointer with strides (1, sy, sz) in elements.
-template <int DT, int INTERP, typename P>
-__device__ __forceinline__ float interp_at(P bp, int sy, int sz, float w0, float w1, float w2) {
-    if (INTERP == 1) {
-        return trilerp(Vox<DT>::dec(bp[0]), Vox<DT>::dec(bp[1]), Vox<DT>::dec(bp[sy]),
-                       Vox<DT>::dec(bp[sy + 1]), Vox<DT>::dec(bp[sz]), Vox<DT>::dec(bp[sz + 1]),
-                       Vox<DT>::dec(bp[sz + sy]), Vox<DT>::dec(bp[sz + sy + 1]), w0, w1, w2);
-    }
-    return Vox<DT>::dec(bp[0]);
-}
-
 template <int DT, int INTERP>
 __device__ __forceinline__ float slot_value(const typename Vox<DT>::T* base, int xch, int lx, int ly,
                                             int lz, float w0, float w1, float w2) {
@@ -384,14 +373,26 @@ __device__ __forceinline__ float pool_value(const DevCube& c, int gx, int gy, in
     return slot_value<DT, INTERP>(base, c.xch, gx & 31, gy & 31, gz & 31, w0, w1, w2);
 }
 
-// Value at element idx of a box staged in LDS, strides (1, sy, sz) elements.
-// 16-bit storage: the pair (x, x+1) is cut from the two aligned dwords that
-// hold it (row strides are multiples of 8 elements, so every row shares the
-// parity of idx), keeping every LDS access dword-aligned.
-template <int DT, int INTERP>
-__device__ __forceinline__ float interp_box(__attribute__((address_space(3))) const typename Vox<DT>::T* box,
-                                            int idx, int sy, int sz, float w0, float w1, float w2) {
-    if (DT == 0 || INTERP == 0) return interp_at<DT, INTERP>(box + idx, sy, sz, w0, w1, w2);
+// The 8 trilinear corners at element idx of a box staged in LDS (strides 1,
+// sy, sz elements), decoded to float.  16-bit storage: each pair (x, x+1) is
+// cut from the two aligned dwords that hold it (row strides are multiples of
+// 8 elements, so every row shares the parity of idx), keeping every LDS
+// access dword-aligned.
+template <int DT>
+__device__ __forceinline__ void box_corners(__attribute__((address_space(3))) const typename Vox<DT>::T* box,
+                                            int idx, int sy, int sz, float c[8]) {
+    if (DT == 0) {
+        const auto* bp = box + idx;
+        c[0] = Vox<DT>::dec(bp[0]);
+        c[1] = Vox<DT>::dec(bp[1]);
+        c[2] = Vox<DT>::dec(bp[sy]);
+        c[3] = Vox<DT>::dec(bp[sy + 1]);
+        c[4] = Vox<DT>::dec(bp[sz]);
+        c[5] = Vox<DT>::dec(bp[sz + 1]);
+        c[6] = Vox<DT>::dec(bp[sz + sy]);
+        c[7] = Vox<DT>::dec(bp[sz + sy + 1]);
+        return;
+    }
     typedef __attribute__((address_space(3))) const uint32_t LW;
     LW* wp = (LW*)box + (idx >> 1);
     const uint32_t sel = (idx & 1) ? 0x05040302u : 0x03020100u;
@@ -400,10 +401,14 @@ __device__ __forceinline__ float interp_box(__attribute__((address_space(3))) co
     const uint32_t p10 = __builtin_amdgcn_perm(wp[hy + 1], wp[hy], sel);
     const uint32_t p01 = __builtin_amdgcn_perm(wp[hz + 1], wp[hz], sel);
     const uint32_t p11 = __builtin_amdgcn_perm(wp[hz + hy + 1], wp[hz + hy], sel);
-    return trilerp(Vox<DT>::dec((uint16_t)p00), Vox<DT>::dec((uint16_t)(p00 >> 16)),
-                   Vox<DT>::dec((uint16_t)p10), Vox<DT>::dec((uint16_t)(p10 >> 16)),
-                   Vox<DT>::dec((uint16_t)p01), Vox<DT>::dec((uint16_t)(p01 >> 16)),
-                   Vox<DT>::dec((uint16_t)p11), Vox<DT>::dec((uint16_t)(p11 >> 16)), w0, w1, w2);
+    c[0] = Vox<DT>::dec((uint16_t)p00);
+    c[1] = Vox<DT>::dec((uint16_t)(p00 >> 16));
+    c[2] = Vox<DT>::dec((uint16_t)p10);
+    c[3] = Vox<DT>::dec((uint16_t)(p10 >> 16));
+    c[4] = Vox<DT>::dec((uint16_t)p01);
+    c[5] = Vox<DT>::dec((uint16_t)(p01 >> 16));
+    c[6] = Vox<DT>::dec((uint16_t)p11);
+    c[7] = Vox<DT>::dec((uint16_t)(p11 >> 16));
 }
 
 // Accumulation state of one ray.
@@ -1170,9 +1175,19 @@ __device__ __forceinline__ bool tile_march(const DevReq& R, const Ray& ray, cons
                     const int pitch = s0.np * CV;
                     const int sy = pitch, sz = pitch * s0.dim[1];
                     const int xoff = s0.lo[0] - s0.xa;
+                    // consecutive samples of a ray often share their cell: its
+                    // corners are read from LDS only when the cell changes (a
+                    // nearest sample's single read is cheaper than the test)
+                    int cidx = -1;
+                    float cc[8];
                     auto fetch = [&](const int* i, const float* w) {
                         const int idx = (int)__umul24(__umul24(i[2], s0.dim[1]) + i[1], pitch) + i[0] + xoff;
-                        return interp_box<DT, INTERP>(box, idx, sy, sz, w[0], w[1], w[2]);
+                        if (INTERP == 0) return Vox<DT>::dec(box[idx]);
+                        if (idx != cidx) {
+                            box_corners<DT>(box, idx, sy, sz, cc);
+                            cidx = idx;
+                        }
+                        return trilerp(cc[0], cc[1], cc[2], cc[3], cc[4], cc[5], cc[6], cc[7], w[0], w[1], w[2]);
                     };
                     if (fine)
                         run(fetch, BoolC<true>());
