@@ -176,6 +176,28 @@ def test_ragged_shapes(R, shape, img, mode):
         R.release(cube)
 
 
+@pytest.mark.parametrize("img", [(16384, 3), (5, 16384)])
+@pytest.mark.parametrize("mode", ["ea", "mip"])
+def test_maximum_image_extents(R, tiny, tiny_cube, img, mode):
+    """Images at the largest width and height the interface accepts (16384):
+    tile grids of 512 x 1 and 1 x 1024 with ragged last tiles; 600 seeded
+    pixels per image, the image's last row and column among them, are
+    compared with the reference."""
+    wl, vol, tf = tiny
+    W, H = img
+    cam = synth.orbit_camera(64, 64, 128, 0.4, 0.3, fovy_deg=40)
+    set_state(R, wl, tf, cam)
+    out = to_np(R.render(tiny_cube, W, H, mode=mode))
+    px = np.concatenate([synth.pixel_subset(900 + W, W, H, 600),
+                         np.array([[W - 1, H - 1], [W - 1, 0], [0, H - 1]], dtype=np.int64)])
+    got = out[px[:, 1], px[:, 0]]
+    ref = ref_render(vol, wl_kwargs(wl, tf), cam, W, H, mode, "trilinear", pixels=px)
+    if mode == "ea":
+        compare_ea(got, ref["values"], TOL_F32, ref["flags"])
+    else:
+        compare_mip(got, ref["values"], TOL_F32, ref["flags"])
+
+
 def test_camera_inside_cube_and_missing_view(R, tiny, tiny_cube):
     wl, vol, tf = tiny
     W, H = 64, 48
