@@ -697,6 +697,21 @@ struct Corners {
     float c[4][2], r[4][2];
 };
 
+// LDS elements per z plane of a box: np chunks per row and d1 rows.  Rows
+// start 16-byte aligned (odd np spreads them over the LDS banks four dwords
+// apart).  When M is x, the lanes of a wave read at nearly the same x and
+// differ in y and z, which leaves them few bank groups; one dword more per
+// plane (global->LDS loads accept dword-aligned LDS addresses) spreads them
+// over all banks.
+template <int M, int CV>
+__device__ __forceinline__ int box_skew() {
+    return M == 0 ? CV / 4 : 0;
+}
+template <int M, int CV>
+__device__ __forceinline__ int box_plane(int np, int d1) {
+    return np * CV * d1 + box_skew<M, CV>();
+}
+
 // One slab: planes [z0, z0 + S] along M, and the box of voxel indices its
 // samples can touch (floor indices plus the +1 neighbour), clamped to the cube.
 struct Slab {
@@ -772,7 +787,7 @@ __device__ __forceinline__ Slab slab_box(int z0, int S, const Corners& cr, const
     s.big = 0;
     s.boff = 0;
     s.late = 0;
-    s.elems = empty ? 0 : s.np * CV * s.dim[1] * s.dim[2];
+    s.elems = empty ? 0 : box_plane<M, CV>(s.np, s.dim[1]) * s.dim[2];
     return s;
 }
 
@@ -984,11 +999,13 @@ __device__ __forceinline__ bool tile_march(const DevReq& R, const Ray& ray, cons
         if (add) atomicAdd(&sh.nact[k & 7], add);
     };
     // Copy a slab's box into its LDS buffer: the box is row-major over
-    // [z][y][16-byte chunk] with np chunks per row, and global->LDS loads write
-    // 16 bytes per lane at consecutive LDS addresses, so each wave instruction
-    // moves rw = 64 / np whole rows (lane l: row l / np, chunk l % np; the
-    // x part of its source address stays fixed for the whole box).  Rows of
-    // more than 64 chunks go one row per instruction group.
+    // [z][y][16-byte chunk] with np chunks per row and planes box_plane()
+    // elements apart, and global->LDS loads write 16 bytes per lane at
+    // consecutive LDS addresses, so each wave instruction moves rw = 64 / np
+    // whole rows, of one plane where planes are not contiguous (lane l: row
+    // l / np, chunk l % np; the x part of its source address stays fixed for
+    // the whole box).  Rows of more than 64 chunks go one row per instruction
+    // group.
     auto staged = [&](const Slab& s) { return s.elems <= (s.big ? 2 * cap : cap); };
     const uint32_t bstride = (uint32_t)R.cube.stride;
     auto row_src = [&](const Slab& s, int iy, int iz) -> const uint8_t* {
@@ -1005,15 +1022,31 @@ __device__ __forceinline__ bool tile_march(const DevReq& R, const Ray& ray, cons
     auto box_dma = [&](const Slab& s) {
         if (s.S == 0 || s.elems == 0 || !staged(s)) return;
         uint8_t* buf = boxes + s.boff;
-        const int np = s.np, d1 = s.dim[1];
-        const int rows = d1 * s.dim[2];
-        const float inv_d1 = 1.0f / (float)d1;
+        const int np = s.np, d1 = s.dim[1], d2 = s.dim[2];
+        const int plane_bytes = box_plane<M, CV>(np, d1) * ELEM;
         if (np <= 64) {
             const float inv_np = 1.0f / (float)np;
             const int rw = div_small(64, np, inv_np);
             const int lr = div_small(lane, np, inv_np);
             const bool on = lr < rw;
             const uint64_t xo = chunk_off(s, lane - lr * np);
+            if (box_skew<M, CV>() != 0) {
+                // planes apart: groups of rw rows of one plane, one instruction each
+                const int gpp = div_small(d1 + rw - 1, rw, 1.0f / (float)rw);  // groups per plane
+                const float inv_gpp = 1.0f / (float)gpp;
+                for (int q = wave; q < gpp * d2; q += VR_NWAVE) {
+                    const int iz = div_small(q, gpp, inv_gpp);
+                    const int y0 = (q - iz * gpp) * rw;
+                    if (on && y0 + lr < d1)
+                        __builtin_amdgcn_global_load_lds((const void*)(row_src(s, y0 + lr, iz) + xo),
+                                                         (__attribute__((address_space(3))) void*)(buf + iz * plane_bytes + y0 * np * 16),
+                                                         16, 0, 0);
+                }
+                return;
+            }
+            // contiguous planes: groups of rw consecutive rows, one instruction each
+            const int rows = d1 * d2;
+            const float inv_d1 = 1.0f / (float)d1;
             const int rstep = VR_NWAVE * rw;
             const int r_first = wave * rw + lr;
             int iz = div_small(r_first, d1, inv_d1);
@@ -1032,13 +1065,15 @@ __device__ __forceinline__ bool tile_march(const DevReq& R, const Ray& ray, cons
                 }
             }
         } else {
+            const int rows = d1 * d2;
+            const float inv_d1 = 1.0f / (float)d1;
             for (int r = wave; r < rows; r += VR_NWAVE) {
-                const int iz = div_small(r, d1, inv_d1);
-                const uint8_t* src = row_src(s, r - iz * d1, iz);
+                const int iz = div_small(r, d1, inv_d1), iy = r - iz * d1;
+                const uint8_t* src = row_src(s, iy, iz);
                 for (int c0 = 0; c0 < np; c0 += 64) {
                     if (c0 + lane < np)
                         __builtin_amdgcn_global_load_lds((const void*)(src + chunk_off(s, c0 + lane)),
-                                                         (__attribute__((address_space(3))) void*)(buf + (r * np + c0) * 16),
+                                                         (__attribute__((address_space(3))) void*)(buf + iz * plane_bytes + (iy * np + c0) * 16),
                                                          16, 0, 0);
                 }
             }
@@ -1173,7 +1208,7 @@ __device__ __forceinline__ bool tile_march(const DevReq& R, const Ray& ray, cons
                 if (staged(s0)) {
                     const LVT* box = (const LVT*)(boxes + s0.boff);
                     const int pitch = s0.np * CV;
-                    const int sy = pitch, sz = pitch * s0.dim[1];
+                    const int sy = pitch, sz = box_plane<M, CV>(s0.np, s0.dim[1]);
                     const int xoff = s0.lo[0] - s0.xa;
                     // consecutive samples of a ray often share their cell: its
                     // corners are read from LDS only when the cell changes (a
@@ -1181,7 +1216,8 @@ __device__ __forceinline__ bool tile_march(const DevReq& R, const Ray& ray, cons
                     int cidx = -1;
                     float cc[8];
                     auto fetch = [&](const int* i, const float* w) {
-                        const int idx = (int)__umul24(__umul24(i[2], s0.dim[1]) + i[1], pitch) + i[0] + xoff;
+                        const int idx = (int)__umul24(__umul24(i[2], s0.dim[1]) + i[1], pitch) + i[0] + xoff +
+                                        i[2] * box_skew<M, CV>();
                         if (INTERP == 0) return Vox<DT>::dec(box[idx]);
                         if (idx != cidx) {
                             box_corners<DT>(box, idx, sy, sz, cc);
