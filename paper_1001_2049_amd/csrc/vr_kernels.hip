@@ -637,14 +637,16 @@ __device__ __forceinline__ void render_lane_direct(const DevReq& R, const int px
 // M, inside the quadrilateral cut by the tile's four corner rays (the tile's
 // rays form a pyramid, or a prism for orthographic views), so the box of voxel
 // indices the samples of a slab can touch follows from the corner rays alone.
-// Each slab's thickness is the largest power of two up to 32 whose box fits a
-// fixed reference size; that choice depends only on the tile's geometry, so
-// the image never depends on staging decisions, batch composition or the LDS
-// the caller leaves free.  The box's 8^3 cells are tested against the skip
-// grid two slabs ahead, the box of the next slab is copied into LDS with
-// 16-byte global->LDS loads while the current slab is sampled, and every lane
-// interpolates its ray's samples of the slab from LDS.  A box larger than its
-// buffer is sampled straight from the brick pool with the same arithmetic.
+// Each slab is the thickest (up to 32 voxels, and at most twice the previous
+// one) whose box fits twice a fixed reference size; that choice depends only
+// on the tile's geometry, so the image never depends on staging decisions,
+// batch composition or the LDS the caller leaves free.  The box's 8^3 cells
+// are tested against the skip grid two slabs ahead, the next slab's box is
+// copied into LDS with 16-byte global->LDS loads once the current slab has
+// been sampled, and every lane interpolates its ray's samples of the slab
+// from LDS, skipping runs of 8 samples whose cells are all inactive where few
+// cells are active.  A box larger than its buffer is sampled straight from
+// the brick pool with the same arithmetic.
 // ---------------------------------------------------------------------------
 #define VR_BIG 0x3fffffff
 #define VR_SMAX 32
