@@ -29,6 +29,7 @@ PEAK_FP32_VECTOR_TFLOPS = 157.3  # MI355X fp32 vector (packed-FMA figure)
 # and the maximum: 37.
 FLOPS_PER_SAMPLE = {"ea": 56, "mip": 37}
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_render_full512_traffic.txt")
+L2_FILE = os.path.join(ROOT, "profiles", "k_render_full512_l2.txt")
 
 
 def log(*a):
@@ -192,6 +193,28 @@ def measured_traffic(kernel_name, width):
     return float(kv["hbm_bytes_per_launch"])
 
 
+def measured_l2(kernel_name, width, kernel_ms):
+    """L2 read traffic of the render kernel from the committed rocprofv3 TCC
+    counter summary, as bytes per launch over this run's measured kernel time,
+    or None when that summary was taken on other kernel source."""
+    try:
+        kv = {}
+        with open(L2_FILE) as f:
+            for line in f:
+                if ":" in line and not line.startswith("#"):
+                    k, v = line.split(":", 1)
+                    kv[k.strip()] = v.strip()
+    except OSError:
+        return None
+    if kv.get("kernel_source_sha256") != kernel_source_digest() or kv.get("kernel") != kernel_name:
+        return None
+    if width != 1024:
+        return None
+    read_bytes = float(kv["l2_read_bytes_per_launch"])
+    return {"read_bytes_per_launch": read_bytes, "hit_rate": float(kv["l2_hit_rate"]),
+            "achieved": round(read_bytes / (kernel_ms * 1e-3) / 1e9, 1), "unit": "GB/s"}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -325,6 +348,8 @@ def main():
             "algorithmic_bytes_per_launch": alg_bytes,
             "traffic": traffic,
         },
+        # L2 reads per launch (TCC counters) over this run's kernel time
+        "l2": measured_l2(kernel_name, W, avg_ms),
     }
     if not args.no_cpu_baseline:
         log("timing the CPU reference")
