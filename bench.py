@@ -20,16 +20,18 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-PEAK_HBM_GBS = 8000.0          # MI355X HBM3E
-PEAK_FP32_VECTOR_TFLOPS = 157.3  # MI355X fp32 vector (packed-FMA figure)
-# Algorithmic floating-point operations per sample (an FMA counts 2): position
-# 3 FMA (6), clamp/floor/fraction 3 x 3 (9), 7 lerps (21), transfer-function
-# index and 4-channel lerp (2 + 8), extinction and opacity (exp + 3), compositing
-# 3 FMA + 1 multiply (7): 56 for EA; MIP keeps position, indexing, the 7 lerps
-# and the maximum: 37.
-FLOPS_PER_SAMPLE = {"ea": 56, "mip": 37}
+PEAK_HBM_GBS = 8000.0  # MI355X HBM3E
+# Vector-ALU issue of the whole chip without packed FP32 (which this build
+# disables): 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz lane-instructions per second.
+PEAK_VALU_LANE_INSTR = 256 * 4 * 16 * 2.4e9
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_render_full512_traffic.txt")
 L2_FILE = os.path.join(ROOT, "profiles", "k_render_full512_l2.txt")
+SQ_FILE = os.path.join(ROOT, "profiles", "k_render_full512_sq.txt")
+# sources that define the render kernels: committed counter summaries carry
+# their digest and are used only while it matches
+KERNEL_SOURCES = ["vr_common.h", "vr_dev.h", "vr_render.h", "vr_render_batch.hip",
+                  "vr_render_ea_f32.hip", "vr_render_ea_f16.hip", "vr_render_ea_bf16.hip",
+                  "vr_render_mip_f32.hip", "vr_render_mip_f16.hip", "vr_render_mip_bf16.hip"]
 
 
 def log(*a):
@@ -37,11 +39,24 @@ def log(*a):
 
 
 def cpu_threads():
+    """Host threads for CPU work: the cores this process may run on, capped at
+    16, the host CPU share that comes with one GPU on the benchmark machines."""
     try:
         n = len(os.sched_getaffinity(0))
     except AttributeError:
         n = os.cpu_count() or 1
     return max(1, min(n, 16))
+
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
 
 def cpu_baseline(vol, tf, wl, cams, W, H, mode, budget_s=12.0, max_views=16):
@@ -64,7 +79,9 @@ def cpu_baseline(vol, tf, wl, cams, W, H, mode, budget_s=12.0, max_views=16):
             break
     return {"value": total / t_all / 1e9, "unit": "Gsamples/s", "cores": th, "kind": "oracle",
             "sample": "%d full %dx%d frame(s) of the same workload (views 0..%d), %.1f s"
-                      % (nviews, W, H, nviews - 1, t_all)}
+                      % (nviews, W, H, nviews - 1, t_all),
+            "host_nproc": os.cpu_count(), "cpu_model": cpu_model(),
+            "ms_per_frame": round(t_all / nviews * 1e3, 1)}
 
 
 def serving_leg(n_requests=256, load=0.7, seed=4242):
@@ -167,26 +184,50 @@ def serving_leg(n_requests=256, load=0.7, seed=4242):
 
 
 def kernel_source_digest():
+    """SHA-256 over the render kernels' sources, in a fixed order."""
     import hashlib
-    path = os.path.join(ROOT, "paper_1001_2049_amd", "csrc", "vr_kernels.hip")
-    with open(path, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()
+    h = hashlib.sha256()
+    for name in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_1001_2049_amd", "csrc", name), "rb") as f:
+            h.update(name.encode() + b"\0" + f.read())
+    return h.hexdigest()
 
 
-def measured_traffic(kernel_name, width):
-    """HBM bytes per launch of the render kernel from the committed rocprofv3
-    counter summary (FETCH_SIZE and WRITE_SIZE scaled by a copy of known
-    size), or None when that summary was taken on other kernel source."""
+def read_summary(path):
+    kv = {}
     try:
-        kv = {}
-        with open(TRAFFIC_FILE) as f:
+        with open(path) as f:
             for line in f:
                 if ":" in line and not line.startswith("#"):
                     k, v = line.split(":", 1)
                     kv[k.strip()] = v.strip()
     except OSError:
         return None
-    if kv.get("kernel_source_sha256") != kernel_source_digest():
+    return kv if kv.get("kernel_source_sha256") == kernel_source_digest() else None
+
+
+def measured_valu(kernel_name, width, samples, kernel_ms):
+    """Vector-ALU roofline of the render kernel from the committed SQ counter
+    summary: wave-level VALU instructions x 64 lanes per nominal sample, over
+    this run's kernel time, against the chip's non-packed issue rate."""
+    kv = read_summary(SQ_FILE)
+    if kv is None or kv.get("kernel") != kernel_name or int(kv.get("image_width", "0")) != width:
+        return None
+    per = float(kv["valu_lane_instr_per_sample"])
+    achieved = per * samples / (kernel_ms * 1e-3)
+    return {"bound": "alu", "lane_instr_per_sample": per,
+            "achieved": round(achieved / 1e12, 3), "peak": round(PEAK_VALU_LANE_INSTR / 1e12, 2),
+            "unit": "T lane-instr/s", "frac": round(achieved / PEAK_VALU_LANE_INSTR, 4),
+            "lds_instr_per_sample": float(kv.get("lds_instr_per_sample", "nan")),
+            "lds_bank_conflict_frac": float(kv.get("lds_bank_conflict_frac", "nan"))}
+
+
+def measured_traffic(kernel_name, width):
+    """HBM bytes per launch of the render kernel from the committed rocprofv3
+    counter summary (FETCH_SIZE and WRITE_SIZE scaled by a copy of known
+    size), or None when that summary was taken on other kernel source."""
+    kv = read_summary(TRAFFIC_FILE)
+    if kv is None:
         return None
     if kv.get("kernel") != kernel_name or int(kv.get("image_width", "0")) != width:
         return None
@@ -197,22 +238,67 @@ def measured_l2(kernel_name, width, kernel_ms):
     """L2 read traffic of the render kernel from the committed rocprofv3 TCC
     counter summary, as bytes per launch over this run's measured kernel time,
     or None when that summary was taken on other kernel source."""
-    try:
-        kv = {}
-        with open(L2_FILE) as f:
-            for line in f:
-                if ":" in line and not line.startswith("#"):
-                    k, v = line.split(":", 1)
-                    kv[k.strip()] = v.strip()
-    except OSError:
-        return None
-    if kv.get("kernel_source_sha256") != kernel_source_digest() or kv.get("kernel") != kernel_name:
+    kv = read_summary(L2_FILE)
+    if kv is None or kv.get("kernel") != kernel_name:
         return None
     if width != 1024:
         return None
     read_bytes = float(kv["l2_read_bytes_per_launch"])
     return {"read_bytes_per_launch": read_bytes, "hit_rate": float(kv["l2_hit_rate"]),
             "achieved": round(read_bytes / (kernel_ms * 1e-3) / 1e9, 1), "unit": "GB/s"}
+
+
+def time_frames(r, cube, cams, W, H, mode, interp, step, ert, reps=1):
+    """Mean kernel ms per frame and nominal samples per frame over the views
+    (events on the launch stream around each render, after one warm-up view)."""
+    import numpy as np
+    import torch
+    stream = torch.cuda.current_stream()
+    out = r.output(W, H, mode)
+    kw = dict(mode=mode, interp=interp, step=step, ert=ert, out=out)
+    nominal = []
+    for cam in cams:
+        r.set_camera(cam)
+        _, st = r.render(cube, W, H, stats=True, **kw)
+        nominal.append(st["samples_nominal"])
+    r.set_camera(cams[0])
+    r.render(cube, W, H, **kw)
+    ms = []
+    for _ in range(reps):
+        for cam in cams:
+            r.set_camera(cam)
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record(stream)
+            r.render(cube, W, H, **kw)
+            b.record(stream)
+            torch.cuda.synchronize()
+            ms.append(a.elapsed_time(b))
+    m = float(np.mean(ms))
+    return {"ms_per_frame": round(m, 4), "gsamples_per_s": round(float(np.mean(nominal)) / m / 1e6, 2),
+            "samples_per_frame": float(np.mean(nominal))}
+
+
+def variants(r, cube_f32, vol, wl, tf, cams, args):
+    """The other configurations of the full-size workload, each timed over the
+    16 orbit views: FP16 / BF16 storage (EA at 1024^2 and 2048^2), and MIP
+    (trilinear and nearest) on the FP32 cube at 1024^2; reported beside the
+    FP32 EA headline on the same GPU."""
+    out = {}
+    kw = dict(step=wl.step, ert=wl.ert)
+    out["f32_mip_trilinear_1024"] = time_frames(r, cube_f32, cams, 1024, 1024, "mip", "trilinear", **kw)
+    out["f32_mip_nearest_1024"] = time_frames(r, cube_f32, cams, 1024, 1024, "mip", "nearest", **kw)
+    out["f32_ea_2048"] = time_frames(r, cube_f32, cams, 2048, 2048, "ea", "trilinear", **kw)
+    for storage in ("f16", "bf16"):
+        c = r.upload(vol, storage)
+        try:
+            for size in (1024, 2048):
+                out["%s_ea_%d" % (storage, size)] = time_frames(r, c, cams, size, size, "ea",
+                                                                 "trilinear", **kw)
+            out["%s_mip_trilinear_1024" % storage] = time_frames(r, c, cams, 1024, 1024, "mip",
+                                                                  "trilinear", **kw)
+        finally:
+            r.release(c)
+    return out
 
 
 def main():
@@ -227,6 +313,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--serving-requests", type=int, default=256)
+    ap.add_argument("--no-variants", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only (--gpus %d requested); the renderer has no "
@@ -290,9 +377,7 @@ def main():
     cube_bytes = wl.cube.nx * wl.cube.ny * wl.cube.nz * elem
     img_bytes = W * H * (16 if args.mode == "ea" else 4)
     alg_bytes = cube_bytes + img_bytes
-    flops_per_sample = FLOPS_PER_SAMPLE[args.mode]
     frame_s = avg_ms * 1e-3
-    alu_achieved = samples / args.steps * flops_per_sample / frame_s / 1e12
     hbm_achieved = alg_bytes / frame_s / 1e9
     kernel_name = "k_render<%s,%s,trilinear>" % (args.mode, args.storage)
     traffic = measured_traffic(kernel_name, W)
@@ -324,33 +409,27 @@ def main():
             "kernel_ms_median": round(float(np.median(kernel_ms)), 4),
             "kernel_ms_p90": round(float(np.percentile(kernel_ms, 90)), 4),
         },
-        # The render is bound by vector-ALU and LDS issue, not by HBM: achieved
-        # is the algorithmic flop count (FLOPS_PER_SAMPLE per nominal sample)
-        # per second against the fp32 vector peak.
+        # The HBM roofline: the compulsory bytes of one frame (the cube read once
+        # plus the image written) over the frame's kernel time, against 8 TB/s.
+        # traffic: HBM bytes per launch from the committed rocprofv3 counters.
         "roofline": {
-            "bound": "alu",
-            "achieved": round(alu_achieved, 3),
-            "peak": PEAK_FP32_VECTOR_TFLOPS,
-            "unit": "TFLOP/s",
-            "frac": round(alu_achieved / PEAK_FP32_VECTOR_TFLOPS, 4),
-            "traffic": traffic,
-            "kernel": kernel_name,
-            "flops_per_sample": flops_per_sample,
-        },
-        # The HBM-roofline fraction: compulsory bytes (the cube once plus the
-        # image) per frame over the frame time, against 8 TB/s.
-        "hbm_roofline": {
             "bound": "hbm",
             "achieved": round(hbm_achieved, 1),
             "peak": PEAK_HBM_GBS,
             "unit": "GB/s",
             "frac": round(hbm_achieved / PEAK_HBM_GBS, 4),
-            "algorithmic_bytes_per_launch": alg_bytes,
             "traffic": traffic,
+            "kernel": kernel_name,
+            "algorithmic_bytes_per_launch": alg_bytes,
         },
+        # vector-ALU issue (wave instructions x 64 lanes, from committed SQ counters)
+        "valu_roofline": measured_valu(kernel_name, W, samples / args.steps, avg_ms),
         # L2 reads per launch (TCC counters) over this run's kernel time
         "l2": measured_l2(kernel_name, W, avg_ms),
     }
+    if not args.no_variants and args.storage == "f32" and W == 1024 and args.mode == "ea":
+        log("configuration variants")
+        res["variants"] = variants(r, cube, vol, wl, tf, cams, args)
     if not args.no_cpu_baseline:
         log("timing the CPU reference")
         res["cpu_baseline"] = cpu_baseline(vol, tf, wl, cams, W, H, args.mode)

@@ -198,30 +198,45 @@ vr_status vr_cube_get_info(vr_ctx ctx, vr_cube cube, vr_cube_info* out);
 
 /* Set the context's transfer function: rgbk holds n rows (r, g, b, kappa),
  * n in [2, 4096], finite, kappa >= 0, spread over [v0, v1] (v1 > v0, data
- * units).  The table is copied. */
+ * units).  The table is copied.  This is the pre-selected transfer function
+ * through which every pixel's ray is mapped to RGBA (paper Sec. 3.1, process
+ * step 3).  Errors: VR_EINVAL for a NULL table or any rule above broken. */
 vr_status vr_set_transfer_function(vr_ctx ctx, const float* rgbk, int32_t n, float v0, float v1);
 
 /* Set the noise clip c = k * sigma (data units).  k = -inf disables it.
- * sigma > 0 and finite. */
+ * sigma > 0 and finite.  Sample values below c are treated as noise and
+ * contribute nothing (EA), or leave a zero pixel when the whole ray stays
+ * below it (MIP): the paper's attention to data of low signal-to-noise ratio
+ * (abstract; Sec. 2).  Errors: VR_EINVAL for NaN or +inf k, or a sigma that
+ * is not positive and finite. */
 vr_status vr_set_noise_clip(vr_ctx ctx, float k, float sigma);
 
 /* Set the camera (validated: finite, up not parallel to the view direction,
- * perspective fovy in (0, 180), orthographic window > 0). */
+ * perspective fovy in (0, 180), orthographic window > 0).  The camera is
+ * the user's view of the cube, turned into a rendering command by the thin
+ * client (paper Fig. 1 caption).  Errors: VR_EINVAL. */
 vr_status vr_set_camera(vr_ctx ctx, const vr_camera* cam);
 
 /* --- rendering ----------------------------------------------------------- */
 
 /* Render `cube` with the context's current state into out_dev (device
  * memory of width*height*4 floats for VR_EA, width*height floats for
- * VR_MIP), enqueued on hip_stream.  With stats != NULL the call waits for
- * the render and fills the counters; otherwise it returns once enqueued.
- * VR_ESTATE if the camera (or, for VR_EA, the transfer function) is unset. */
+ * VR_MIP), enqueued on hip_stream.  One ray is cast per pixel (ray casting
+ * is design decision 1 of the paper's Sec. 2; each pixel is mapped to RGBA
+ * through the transfer function, Sec. 3.1 process step 3).  With stats !=
+ * NULL the call waits for the render and fills the counters; otherwise it
+ * returns once enqueued.  The caller keeps out_dev alive until hip_stream
+ * has reached the render.  Errors: VR_EINVAL (parameters, NULL out_dev),
+ * VR_ENOTFOUND (cube), VR_ESTATE if the camera (or, for VR_EA, the transfer
+ * function) is unset, VR_EDEVICE on a HIP error. */
 vr_status vr_render(vr_ctx ctx, vr_cube cube, const vr_render_params* params, void* out_dev,
                     void* hip_stream, vr_stats* stats);
 
 /* --- batched rendering and serving ---------------------------------------- */
 
-/* Transfer functions as objects, for requests that carry their own. */
+/* Transfer functions as objects, for requests that carry their own
+ * (rules and citation as for vr_set_transfer_function).  vr_tf_release gives
+ * VR_EBUSY while queued requests or the context's current state hold it. */
 vr_status vr_tf_create(vr_ctx ctx, const float* rgbk, int32_t n, float v0, float v1, vr_tf* out);
 vr_status vr_tf_release(vr_ctx ctx, vr_tf tf);
 
@@ -240,18 +255,25 @@ typedef struct {
 /* Render `count` requests (up to 4096; any mix of cubes, sizes, modes) in one
  * persistent launch on hip_stream.  Each image equals what the request gives
  * when rendered alone in a batch of one.  Optional per-request stats as in
- * vr_render (the call then waits). */
+ * vr_render (the call then waits).  This is the one-GPU form of the paper's
+ * scheduler, which maps rendering tasks onto the available GPUs (Fig. 1
+ * caption; Sec. 3.1 process step 2).  Errors as for vr_render, per request
+ * (the message names the request). */
 vr_status vr_render_batch(vr_ctx ctx, const vr_request* reqs, int32_t count, void* hip_stream,
                           vr_stats* stats);
 
 typedef struct {
     int32_t max_batch_requests; /* requests admitted per launch (1..4096) */
-    int32_t max_batch_tiles;    /* 16x16-pixel tiles per launch (>= 1) */
+    int32_t max_batch_tiles;    /* workgroup tiles (32x16 pixels each) per launch (>= 1) */
     int32_t max_inflight;       /* launches in flight (1..4) */
     int32_t use_graphs;         /* 1: replay a captured graph per shape class */
 } vr_server_cfg;
 
-/* Start/stop the serving loop (a host thread owned by the context). */
+/* Start/stop the serving loop (a host thread owned by the context): the
+ * scheduler server of the paper's framework (Fig. 1 caption), here batching
+ * concurrent view requests into persistent launches on one GPU.  Start gives
+ * VR_ESTATE if a server already runs, VR_EINVAL for a config out of range;
+ * stop waits for queued work and is a no-op without a server. */
 vr_status vr_server_start(vr_ctx ctx, const vr_server_cfg* cfg);
 vr_status vr_server_stop(vr_ctx ctx);
 

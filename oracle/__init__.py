@@ -74,7 +74,8 @@ def lib():
             build(force=False)
         L = ctypes.CDLL(_LIB_PATH)
         P = ctypes.c_void_p
-        L.orc_render.argtypes = [ctypes.POINTER(Scene), ctypes.c_int64, P, P, P, P, P, ctypes.c_int]
+        L.orc_render.argtypes = [ctypes.POINTER(Scene), ctypes.c_int64, P, P, P, P, P, P,
+                                 ctypes.c_int]
         L.orc_render.restype = ctypes.c_int
         L.orc_decode_f16.argtypes = [ctypes.c_uint16]
         L.orc_decode_f16.restype = ctypes.c_double
@@ -163,7 +164,9 @@ def render(vol, *, pixels=None, threads=None, **kw):
 
     Returns a dict with ``image`` (H, W, 4) / (H, W) for full images or
     ``values`` (npix, 4) / (npix,) for pixel lists, plus ``n_nominal``,
-    ``n_exec`` and ``flags`` with matching leading shape.
+    ``n_exec`` and ``flags`` with matching leading shape; for MIP also
+    ``bounds`` (..., 2): the least and greatest correct maximum where nearest
+    sampling meets rounding ties (equal to the value elsewhere).
     """
     S = make_scene(vol, **kw)
     W, H = S.width, S.height
@@ -178,19 +181,25 @@ def render(vol, *, pixels=None, threads=None, **kw):
     nn = np.zeros(npix, dtype=np.int64)
     ne = np.zeros(npix, dtype=np.int64)
     fl = np.zeros(npix, dtype=np.int32)
+    bd = np.zeros((npix, 2), dtype=np.float64) if ch == 1 else None
     rc = lib().orc_render(ctypes.byref(S), npix, px.ctypes.data if px is not None else None,
                           out.ctypes.data, nn.ctypes.data, ne.ctypes.data, fl.ctypes.data,
+                          bd.ctypes.data if bd is not None else None,
                           threads or default_threads())
     if rc != 0:
         raise ValueError("orc_render rejected its arguments")
     if ch == 1:
         out = out[:, 0]
     res = {"n_nominal": nn, "n_exec": ne, "flags": fl}
+    if bd is not None:
+        res["bounds"] = bd
     if pixels is None:
         res["image"] = out.reshape((H, W, 4) if ch == 4 else (H, W))
         res["n_nominal"] = nn.reshape(H, W)
         res["n_exec"] = ne.reshape(H, W)
         res["flags"] = fl.reshape(H, W)
+        if bd is not None:
+            res["bounds"] = bd.reshape(H, W, 2)
     else:
         res["values"] = out
     return res

@@ -189,23 +189,44 @@ static inline double clampd(double x, double lo, double hi) {
 }
 static inline double lerp(double a, double b, double f) { return a + f * (b - a); }
 
-/* Sample value at p; sets *tie when nearest rounding is within the margin of a tie. */
-static double sample(const orc_scene* S, const double p[3], int* tie) {
+/* Sample value at p; sets *tie when nearest rounding is within the margin of a
+ * tie.  For nearest sampling, *vlo and *vhi (when non-NULL) receive the least
+ * and greatest value over every voxel a tied coordinate could round to (both
+ * equal the sample when there is no tie): the set of correct samples. */
+static double sample(const orc_scene* S, const double p[3], int* tie, double* vlo, double* vhi) {
     const int64_t N[3] = {S->nx, S->ny, S->nz};
     if (S->interp == ORC_NEAREST) {
-        int64_t i[3];
+        int64_t i[3], alt[3];
         for (int a = 0; a < 3; ++a) {
             double s = p[a] + 0.5;
             double fl = floor(s);
             double fr = s - fl;
-            if (s > 0.0 && s < (double)N[a] && (fr < S->amb_nearest || fr > 1.0 - S->amb_nearest))
-                *tie = 1;
             int64_t k = (int64_t)fl;
+            int64_t k2 = k;
+            if (s > 0.0 && s < (double)N[a] && (fr < S->amb_nearest || fr > 1.0 - S->amb_nearest)) {
+                *tie = 1;
+                k2 = fr < 0.5 ? k - 1 : k + 1;  /* the other side of the tie */
+            }
             if (k < 0) k = 0;
             if (k > N[a] - 1) k = N[a] - 1;
+            if (k2 < 0) k2 = 0;
+            if (k2 > N[a] - 1) k2 = N[a] - 1;
             i[a] = k;
+            alt[a] = k2;
         }
-        return voxel(S, i[0], i[1], i[2]);
+        double v = voxel(S, i[0], i[1], i[2]);
+        if (vlo && vhi) {
+            double lo = v, hi = v;
+            for (int c = 1; c < 8; ++c) {
+                double w = voxel(S, (c & 1) ? alt[0] : i[0], (c & 2) ? alt[1] : i[1],
+                                 (c & 4) ? alt[2] : i[2]);
+                if (w < lo) lo = w;
+                if (w > hi) hi = w;
+            }
+            *vlo = lo;
+            *vhi = hi;
+        }
+        return v;
     }
     int64_t i[3];
     double f[3];
@@ -223,7 +244,9 @@ static double sample(const orc_scene* S, const double p[3], int* tie) {
     double x00 = lerp(c000, c100, f[0]), x10 = lerp(c010, c110, f[0]);
     double x01 = lerp(c001, c101, f[0]), x11 = lerp(c011, c111, f[0]);
     double y0 = lerp(x00, x10, f[1]), y1 = lerp(x01, x11, f[1]);
-    return lerp(y0, y1, f[2]);
+    double v = lerp(y0, y1, f[2]);
+    if (vlo && vhi) *vlo = *vhi = v;
+    return v;
 }
 
 /* Transfer-function row (r, g, b, kappa) for value v (no clip). */
@@ -236,9 +259,10 @@ void orc_classify(const orc_scene* S, double v, double out[4]) {
     for (int c = 0; c < 4; ++c) out[c] = lerp(S->tf[4 * i0 + c], S->tf[4 * (i0 + 1) + c], g);
 }
 
-/* One ray.  out: 4 doubles (EA) or 1 (MIP). */
+/* One ray.  out: 4 doubles (EA) or 1 (MIP).  bounds (MIP, nullable): the least
+ * and greatest maximum over the correct choices at nearest-sampling ties. */
 void orc_ray(const orc_scene* S, int64_t pi, int64_t pj, double* out, int64_t* n_nominal,
-             int64_t* n_exec, int32_t* flags) {
+             int64_t* n_exec, int32_t* flags, double* bounds) {
     double o[3], d[3], tin, tout;
     int32_t fl = 0;
     int64_t nn = 0, ne = 0;
@@ -247,6 +271,7 @@ void orc_ray(const orc_scene* S, int64_t pi, int64_t pj, double* out, int64_t* n
     if (!orc_slab(S, o, d, &tin, &tout)) {
         if (mip) out[0] = -INFINITY;
         else out[0] = out[1] = out[2] = out[3] = 0.0;
+        if (bounds) bounds[0] = bounds[1] = -INFINITY;
         goto done;
     }
     fl |= ORC_FLAG_HIT;
@@ -263,7 +288,7 @@ void orc_ray(const orc_scene* S, int64_t pi, int64_t pj, double* out, int64_t* n
             orc_classify(S, S->clip, rc);
             clip_jump = rc[3] > 0.0;
         }
-        double C[3] = {0.0, 0.0, 0.0}, T = 1.0, m = -INFINITY;
+        double C[3] = {0.0, 0.0, 0.0}, T = 1.0, m = -INFINITY, m_lo = -INFINITY, m_hi = -INFINITY;
         for (int64_t k = 0; k < n; ++k) {
             double a = tin + (double)k * step;
             double b = tin + (double)(k + 1) * step;
@@ -272,11 +297,14 @@ void orc_ray(const orc_scene* S, int64_t pi, int64_t pj, double* out, int64_t* n
             double tm = a + 0.5 * len;
             double p[3] = {o[0] + tm * d[0], o[1] + tm * d[1], o[2] + tm * d[2]};
             int tie = 0;
-            double v = sample(S, p, &tie);
+            double vlo, vhi;
+            double v = sample(S, p, &tie, &vlo, &vhi);
             if (tie) fl |= ORC_FLAG_NEAREST_AMBIG;
             ++ne;
             if (mip) {
                 if (v > m) m = v;
+                if (vlo > m_lo) m_lo = vlo;
+                if (vhi > m_hi) m_hi = vhi;
                 continue;
             }
             if (clip_jump && fabs(v - S->clip) < S->amb_clip * fmax(1.0, fabs(S->clip)))
@@ -297,6 +325,10 @@ void orc_ray(const orc_scene* S, int64_t pi, int64_t pj, double* out, int64_t* n
             if (isfinite(S->clip) && fabs(m - S->clip) < S->amb_clip * fmax(1.0, fabs(S->clip)))
                 fl |= ORC_FLAG_MIPCLIP_AMBIG;
             out[0] = (m >= S->clip) ? m : 0.0;
+            if (bounds) {
+                bounds[0] = m_lo;
+                bounds[1] = m_hi;
+            }
         } else {
             out[0] = C[0]; out[1] = C[1]; out[2] = C[2]; out[3] = 1.0 - T;
         }
@@ -316,6 +348,7 @@ typedef struct {
     int64_t* nn;
     int64_t* ne;
     int32_t* flags;
+    double* bounds;
     volatile int64_t* next;
 } drv_t;
 
@@ -333,7 +366,8 @@ static void* drv_worker(void* arg) {
             if (D->px) { i = D->px[2 * p]; j = D->px[2 * p + 1]; }
             else { i = p % D->S->width; j = p / D->S->width; }
             orc_ray(D->S, i, j, D->out + ch * p, D->nn ? D->nn + p : NULL,
-                    D->ne ? D->ne + p : NULL, D->flags ? D->flags + p : NULL);
+                    D->ne ? D->ne + p : NULL, D->flags ? D->flags + p : NULL,
+                    D->bounds ? D->bounds + 2 * p : NULL);
         }
     }
     return NULL;
@@ -342,11 +376,13 @@ static void* drv_worker(void* arg) {
 /*
  * Render npix pixels (px = NULL: the whole width x height image in row-major
  * order).  out holds 4 doubles per pixel (EA) or 1 (MIP).  Optional per-pixel
- * outputs: nominal sample count, executed sample count, flags.
+ * outputs: nominal sample count, executed sample count, flags, and (MIP) the
+ * bounds of the correct maxima at nearest-sampling ties (2 doubles).
  * Returns 0, or -1 on invalid arguments.
  */
 int orc_render(const orc_scene* S, int64_t npix, const int32_t* px, double* out,
-               int64_t* n_nominal, int64_t* n_exec, int32_t* flags, int nthreads) {
+               int64_t* n_nominal, int64_t* n_exec, int32_t* flags, double* bounds,
+               int nthreads) {
     if (!S || !out || !S->vox || S->nx < 2 || S->ny < 2 || S->nz < 2) return -1;
     if (S->width < 1 || S->height < 1 || !(S->step > 0.0)) return -1;
     if (S->mode == ORC_EA && (!S->tf || S->tf_n < 2 || !(S->v1 > S->v0))) return -1;
@@ -360,7 +396,7 @@ int orc_render(const orc_scene* S, int64_t npix, const int32_t* px, double* out,
     if (nthreads < 1) nthreads = 1;
     if (nthreads > 256) nthreads = 256;
     volatile int64_t next = 0;
-    drv_t D = {S, npix, px, out, n_nominal, n_exec, flags, &next};
+    drv_t D = {S, npix, px, out, n_nominal, n_exec, flags, bounds, &next};
     pthread_t th[256];
     int started = 0;
     for (int t = 0; t < nthreads; ++t) {

@@ -1,7 +1,8 @@
 """Build the renderer's shared library (libvr.so) with hipcc for gfx950.
 
-Every HIP/C++ source under csrc/ is compiled into one position-independent
-shared object next to this file.  Packed FP32 instructions are disabled on
+Every HIP/C++ source under csrc/ is compiled (in parallel, one process per
+translation unit) into one position-independent shared object next to this
+file.  Packed FP32 instructions are disabled on
 purpose (-packed-fp32-ops); the host pass warns that it does not know the
 feature, which is harmless.
 """
@@ -10,12 +11,15 @@ from __future__ import annotations
 import os
 import subprocess
 import sys
+from concurrent.futures import ThreadPoolExecutor
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(os.path.dirname(HERE), "include")
 LIB = os.path.join(HERE, "libvr.so")
-SOURCES = ["vr_kernels.hip", "vr_capi.cpp", "vr_server.cpp"]
+SOURCES = ["vr_render_batch.hip", "vr_render_ea_f32.hip", "vr_render_ea_f16.hip",
+           "vr_render_ea_bf16.hip", "vr_render_mip_f32.hip", "vr_render_mip_f16.hip",
+           "vr_render_mip_bf16.hip", "vr_kernels.hip", "vr_capi.cpp", "vr_server.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
@@ -25,15 +29,21 @@ FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
 def build(verbose: bool = False) -> str:
     build_dir = os.path.join(HERE, "_build")
     os.makedirs(build_dir, exist_ok=True)
-    objs = []
+    cmds, objs = [], []
     for src in SOURCES:
         obj = os.path.join(build_dir, os.path.splitext(src)[0] + ".o")
         lang = [] if src.endswith(".hip") else ["-x", "hip"]
-        cmd = [HIPCC, *FLAGS, *lang, "-c", os.path.join(CSRC, src), "-o", obj]
+        cmds.append([HIPCC, *FLAGS, *lang, "-c", os.path.join(CSRC, src), "-o", obj])
+        objs.append(obj)
+
+    def run(cmd):
         if verbose:
             print(" ".join(cmd), flush=True)
         subprocess.check_call(cmd)
-        objs.append(obj)
+
+    jobs = max(1, min(len(cmds), int(os.environ.get("MAX_JOBS", "0")) or (os.cpu_count() or 1)))
+    with ThreadPoolExecutor(max_workers=jobs) as ex:
+        list(ex.map(run, cmds))
     tmp = LIB + ".tmp%d" % os.getpid()
     cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp, *objs, "-lpthread"]
     if verbose:

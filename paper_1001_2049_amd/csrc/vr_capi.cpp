@@ -24,6 +24,44 @@ vr_status hip_check(hipError_t e, const char* what) {
     return VR_EDEVICE;
 }
 
+vr_status Uses::record(hipStream_t s) {
+    for (auto& e : ev)
+        if (e.first == s) return hip_check(hipEventRecord(e.second, s), "hipEventRecord");
+    if (ev.size() >= 16) {
+        // bound the list: once every older use is complete, it can be dropped
+        vr_status st = sync();
+        if (st != VR_OK) return st;
+        destroy();
+    }
+    hipEvent_t e = nullptr;
+    vr_status st = hip_check(hipEventCreateWithFlags(&e, hipEventDisableTiming), "hipEventCreate");
+    if (st != VR_OK) return st;
+    ev.emplace_back(s, e);
+    return hip_check(hipEventRecord(e, s), "hipEventRecord");
+}
+
+vr_status Uses::wait_on(hipStream_t s) const {
+    for (const auto& e : ev) {
+        if (e.first == s) continue;  // stream order already covers it
+        vr_status st = hip_check(hipStreamWaitEvent(s, e.second, 0), "hipStreamWaitEvent");
+        if (st != VR_OK) return st;
+    }
+    return VR_OK;
+}
+
+vr_status Uses::sync() const {
+    for (const auto& e : ev) {
+        vr_status st = hip_check(hipEventSynchronize(e.second), "hipEventSynchronize");
+        if (st != VR_OK) return st;
+    }
+    return VR_OK;
+}
+
+void Uses::destroy() {
+    for (auto& e : ev) (void)hipEventDestroy(e.second);
+    ev.clear();
+}
+
 uint64_t Cube::bytes() const {
     uint64_t b = pool.bytes + cellmm.bytes;
     for (const auto& m : masks) b += m.buf.bytes + m.bits.bytes;
@@ -236,6 +274,9 @@ static vr_status get_mask(Ctx* c, Cube* cube, int mode, Tf* tf, float clip_s, hi
     std::memcpy(&cb, &clip_s, 4);
     for (auto& m : cube->masks) {
         if (m.mode == mode && m.tf_version == ver && m.clip_bits == cb) {
+            // the classification that filled it may have been enqueued on another stream
+            vr_status st = hip_check(hipStreamWaitEvent(s, m.ready, 0), "hipStreamWaitEvent");
+            if (st != VR_OK) return st;
             m.stamp = ++c->mask_stamp;
             *out = &m;
             return VR_OK;
@@ -258,12 +299,12 @@ static vr_status get_mask(Ctx* c, Cube* cube, int mode, Tf* tf, float clip_s, hi
             cube->masks.pop_back();
             return st;
         }
-        st = ensure_event(e->last_use);
+        st = ensure_event(e->ready);
         if (st != VR_OK) return st;
     } else {
         e = lru;
-        // the entry may still be read by queued work on another stream
-        vr_status st = hip_check(hipStreamWaitEvent(s, e->last_use, 0), "hipStreamWaitEvent");
+        // the entry may still be read by queued work on any stream that used it
+        vr_status st = e->uses.wait_on(s);
         if (st != VR_OK) return st;
     }
     float scale = 1.0f, bias = 0.0f;
@@ -281,6 +322,7 @@ static vr_status get_mask(Ctx* c, Cube* cube, int mode, Tf* tf, float clip_s, hi
                            (uint32_t*)e->bits.ptr, cube->Bx, cube->By, cube->Bz, mode, clip_s, scale,
                            bias, n, kpos, s),
         "classify launch");
+    if (st == VR_OK) st = hip_check(hipEventRecord(e->ready, s), "hipEventRecord");
     if (st != VR_OK) return st;
     e->mode = mode;
     e->tf_version = ver;
@@ -349,21 +391,10 @@ vr_status build_request(Ctx* c, Cube* cube, Tf* tf, float clip, const vr_camera&
 
 vr_status mark_use(Ctx* c, Cube* cube, Tf* tf, MaskEntry* mask, hipStream_t s) {
     (void)c;
-    vr_status st = ensure_event(cube->last_use);
-    if (st != VR_OK) return st;
-    st = hip_check(hipEventRecord(cube->last_use, s), "hipEventRecord");
-    if (st != VR_OK) return st;
-    if (mask) {
-        st = hip_check(hipEventRecord(mask->last_use, s), "hipEventRecord");
-        if (st != VR_OK) return st;
-    }
-    if (tf) {
-        st = ensure_event(tf->last_use);
-        if (st != VR_OK) return st;
-        st = hip_check(hipEventRecord(tf->last_use, s), "hipEventRecord");
-        if (st != VR_OK) return st;
-    }
-    return VR_OK;
+    vr_status st = cube->uses.record(s);
+    if (st == VR_OK && mask) st = mask->uses.record(s);
+    if (st == VR_OK && tf) st = tf->uses.record(s);
+    return st;
 }
 
 static vr_status ensure_counters(Ctx* c, int count) {
@@ -670,11 +701,9 @@ static vr_status make_tf(Ctx* c, const float* rgbk, int32_t n, float v0, float v
 }
 
 static vr_status release_tf(Ctx* c, Tf* t) {
-    if (t->last_use) {
-        vr_status st = hip_check(hipEventSynchronize(t->last_use), "hipEventSynchronize");
-        if (st != VR_OK) return st;
-        (void)hipEventDestroy(t->last_use);
-    }
+    vr_status st = t->uses.sync();
+    if (st != VR_OK) return st;
+    t->uses.destroy();
     dev_free(c, t->dev_rows, false);
     dev_free(c, t->dev_kpos, false);
     c->tfs.erase(t->id);
@@ -682,15 +711,16 @@ static vr_status release_tf(Ctx* c, Tf* t) {
 }
 
 static vr_status release_cube(Ctx* c, Cube* cube) {
-    if (cube->last_use) {
-        vr_status st = hip_check(hipEventSynchronize(cube->last_use), "hipEventSynchronize");
-        if (st != VR_OK) return st;
-        (void)hipEventDestroy(cube->last_use);
-    }
+    vr_status st = cube->uses.sync();
+    for (auto& m : cube->masks)
+        if (st == VR_OK) st = m.uses.sync();
+    if (st != VR_OK) return st;
+    cube->uses.destroy();
     for (auto& m : cube->masks) {
         dev_free(c, m.buf, true);
         dev_free(c, m.bits, true);
-        if (m.last_use) (void)hipEventDestroy(m.last_use);
+        m.uses.destroy();
+        if (m.ready) (void)hipEventDestroy(m.ready);
     }
     dev_free(c, cube->pool, true);
     dev_free(c, cube->cellmm, true);

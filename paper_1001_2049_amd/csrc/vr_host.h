@@ -31,13 +31,26 @@ struct DevBuf {
     uint64_t bytes = 0;
 };
 
+// Work that reads an object, tracked with one event per stream that used it:
+// the object may be freed or rewritten only once every stream's last use has
+// completed (a single "last use" event would miss earlier readers on other
+// streams).
+struct Uses {
+    std::vector<std::pair<hipStream_t, hipEvent_t>> ev;
+    vr_status record(hipStream_t s);        // after the work just enqueued on s
+    vr_status wait_on(hipStream_t s) const; // make s wait for every recorded use
+    vr_status sync() const;                 // the host waits for every recorded use
+    void destroy();
+};
+
 struct MaskEntry {
     int mode = 0;
     int64_t tf_version = -1;
     uint32_t clip_bits = 0;
     DevBuf buf;                     // per slot 64-bit masks
     DevBuf bits;                    // per-cell grid
-    hipEvent_t last_use = nullptr;  // last work reading this mask
+    hipEvent_t ready = nullptr;     // recorded after the classification that filled it
+    Uses uses;                      // work reading it
     uint64_t stamp = 0;
 };
 
@@ -52,7 +65,7 @@ struct Cube {
     uint64_t stride = 0;
     DevBuf pool, cellmm;
     std::deque<MaskEntry> masks;    // deque: entries never move while requests point at them
-    hipEvent_t last_use = nullptr;  // last work reading this cube
+    Uses uses;                      // work reading this cube
     int refs = 0;                   // queued serving requests
     uint64_t bytes() const;
 };
@@ -65,7 +78,7 @@ struct Tf {
     std::vector<float> rows;  // n x 4
     DevBuf dev_rows;          // 2n float4: row, next row - row
     DevBuf dev_kpos;          // n + 2 ints: prefix counts of kappa > 0
-    hipEvent_t last_use = nullptr;
+    Uses uses;                // work reading this table
     bool internal = false;    // created by vr_set_transfer_function
     int refs = 0;             // queued serving requests
 };
@@ -115,7 +128,9 @@ struct Ctx {
     hipEvent_t order_done = nullptr;  // last render that read `order`
     BatchBufs batch;
 
-    Server* server = nullptr;
+    // The server is shared with callers blocked in vr_wait / vr_poll, so that a
+    // concurrent vr_server_stop cannot free it under them.
+    std::shared_ptr<Server> server;
     std::mutex server_mu;       // guards server start/stop
 
     bool host_only() const { return device < 0; }

@@ -1,0 +1,1197 @@
+// vr_render.h — the per-tile render machinery (ray set-up, slab staging,
+// sampling, classification, compositing, store) and the single-image
+// kernel template.  Included by the translation units that instantiate the
+// kernels (one per render mode and storage format, and the batched kernel),
+// so that they compile in parallel.
+#pragma once
+
+#include "vr_common.h"
+#include "vr_launch.h"
+
+// ---------------------------------------------------------------------------
+// Rendering: shared pieces
+// ---------------------------------------------------------------------------
+struct LaneCounts {
+    unsigned nominal, exec, hit, ert, skipped;
+};
+
+// One ray: origin/direction and chord in float-float, the sample lattice.
+struct Ray {
+    ff o[3], d[3];
+    ff tin;
+    int n;                 // lattice samples; 0 when the ray misses the cube
+    float last_adj;        // the last segment's midpoint, in lattice steps before a full step's
+    float c_full, c_last;  // -len * log2(e) of full and last segments
+    float dd[3];           // step * direction
+};
+
+// Ray through pixel-centre coordinates (fi, fj).  Both camera kinds produce
+// scalar values that are stored once, after the branch (stores sunk out of
+// the two branches would otherwise select between stack addresses).
+__device__ __forceinline__ void ray_dir(const DevCam& cam, float fi, float fj, ff o[3], ff d[3]) {
+    ff o0, o1, o2, d0, d1, d2;
+    if (cam.ortho) {
+        o0 = ff_add(ff_add(cam.o[0], ff_mul_f(cam.dx[0], fi)), ff_mul_f(cam.dy[0], fj));
+        o1 = ff_add(ff_add(cam.o[1], ff_mul_f(cam.dx[1], fi)), ff_mul_f(cam.dy[1], fj));
+        o2 = ff_add(ff_add(cam.o[2], ff_mul_f(cam.dx[2], fi)), ff_mul_f(cam.dy[2], fj));
+        d0 = cam.dir[0];
+        d1 = cam.dir[1];
+        d2 = cam.dir[2];
+    } else {
+        const ff e0 = ff_add(ff_add(cam.base[0], ff_mul_f(cam.dx[0], fi)), ff_mul_f(cam.dy[0], fj));
+        const ff e1 = ff_add(ff_add(cam.base[1], ff_mul_f(cam.dx[1], fi)), ff_mul_f(cam.dy[1], fj));
+        const ff e2 = ff_add(ff_add(cam.base[2], ff_mul_f(cam.dx[2], fi)), ff_mul_f(cam.dy[2], fj));
+        const ff n2 = ff_add(ff_add(ff_mul(e0, e0), ff_mul(e1, e1)), ff_mul(e2, e2));
+        const ff inv = ff_div(ff_make(1.0f), ff_sqrt(n2));
+        d0 = ff_mul(e0, inv);
+        d1 = ff_mul(e1, inv);
+        d2 = ff_mul(e2, inv);
+        o0 = cam.o[0];
+        o1 = cam.o[1];
+        o2 = cam.o[2];
+    }
+    o[0] = o0;
+    o[1] = o1;
+    o[2] = o2;
+    d[0] = d0;
+    d[1] = d1;
+    d[2] = d2;
+}
+
+// Camera ray of pixel (px, py), its chord through [-1/2, N-1/2]^3 and the
+// lattice of n = ceil(L/step) segments sampled at their midpoints.
+__device__ __forceinline__ void ray_setup(const DevReq& R, int px, int py, Ray& ray) {
+    ray_dir(R.cam, (float)px + 0.5f, (float)py + 0.5f, ray.o, ray.d);
+    const int N[3] = {R.cube.nx, R.cube.ny, R.cube.nz};
+    ff tin = ff_make(R.cam.ortho ? -VR_INF : 0.0f);
+    ff tout = ff_make(VR_INF);
+    bool hit = true;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const float hib = (float)N[a] - 0.5f;
+        if (ray.d[a].hi != 0.0f) {
+            const ff t0 = ff_div(ff_sub(ff_make(-0.5f), ray.o[a]), ray.d[a]);
+            const ff t1 = ff_div(ff_sub(ff_make(hib), ray.o[a]), ray.d[a]);
+            tin = ff_max(tin, ff_min(t0, t1));
+            tout = ff_min(tout, ff_max(t0, t1));
+        } else if (ff_lt(ray.o[a], ff_make(-0.5f)) || ff_lt(ff_make(hib), ray.o[a])) {
+            hit = false;
+        }
+    }
+    hit = hit && ff_lt(tin, tout);
+    if (!hit) {
+        ray.n = 0;
+        return;
+    }
+    const ff L = ff_sub(tout, tin);
+    const ff rr = ff_div(L, R.step);
+    float nf = ceilf(rr.hi);
+    if (nf == rr.hi && rr.lo > 0.0f) nf += 1.0f;
+    ray.n = nf < 1.0f ? 1 : (int)nf;
+    ray.tin = tin;
+    const float stepf = ff_to_f(R.step);
+    float len_last = ff_to_f(ff_sub(L, ff_mul_f(R.step, (float)(ray.n - 1))));
+    len_last = fmaxf(len_last, 0.0f);
+    ray.last_adj = 0.5f * (len_last / stepf - 1.0f);
+    ray.c_full = -stepf * VR_LOG2E;
+    ray.c_last = -len_last * VR_LOG2E;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) ray.dd[a] = ff_to_f(ff_mul(ray.d[a], R.step));
+}
+
+// Parameter t of lattice sample k.
+__device__ __forceinline__ ff sample_t(const DevReq& R, const Ray& ray, int k) {
+    ff t = ff_add(ray.tin, ff_mul_f(R.step, (float)k + 0.5f));
+    if (k == ray.n - 1) t = ff_add(t, ff_make(ray.last_adj * ff_to_f(R.step)));
+    return t;
+}
+
+// Element offsets of local voxel coordinates inside a slot (separable).
+template <int DT>
+__device__ __forceinline__ int slot_x(int lx) {
+    constexpr int CV = DT == 0 ? 4 : 8;
+    return (lx / CV) * 8 * CV + lx % CV;
+}
+template <int DT>
+__device__ __forceinline__ int slot_y(int ly, int xch) {
+    constexpr int CV = DT == 0 ? 4 : 8;
+    return (ly >> 2) * xch * 8 * CV + (ly & 3) * CV;
+}
+template <int DT>
+__device__ __forceinline__ int slot_z(int lz, int xch) {
+    constexpr int CV = DT == 0 ? 4 : 8;
+    return (lz >> 1) * VR_SLOT_YG * xch * 8 * CV + (lz & 1) * 4 * CV;
+}
+
+// Interpolated value at local voxel (lx, ly, lz) of a slot with weights w;
+// the +1 neighbours are in the same slot thanks to the apron.
+template <int DT, int INTERP>
+__device__ __forceinline__ float slot_value(const typename Vox<DT>::T* base, int xch, int lx, int ly,
+                                            int lz, float w0, float w1, float w2);
+
+// Trilinear interpolation of the 8 corners (x, then y, then z).
+__device__ __forceinline__ float trilerp(float c000, float c100, float c010, float c110, float c001,
+                                         float c101, float c011, float c111, float w0, float w1,
+                                         float w2) {
+    const float x00 = __builtin_fmaf(w0, c100 - c000, c000);
+    const float x10 = __builtin_fmaf(w0, c110 - c010, c010);
+    const float x01 = __builtin_fmaf(w0, c101 - c001, c001);
+    const float x11 = __builtin_fmaf(w0, c111 - c011, c011);
+    const float y0 = __builtin_fmaf(w1, x10 - x00, x00);
+    const float y1 = __builtin_fmaf(w1, x11 - x01, x01);
+    return __builtin_fmaf(w2, y1 - y0, y0);
+}
+
+template <int DT, int INTERP>
+__device__ __forceinline__ float slot_value(const typename Vox<DT>::T* base, int xch, int lx, int ly,
+                                            int lz, float w0, float w1, float w2) {
+    const int x0 = slot_x<DT>(lx), y0 = slot_y<DT>(ly, xch), z0 = slot_z<DT>(lz, xch);
+    if (INTERP == 0) return Vox<DT>::dec(base[x0 + y0 + z0]);
+    const int x1 = slot_x<DT>(lx + 1), y1 = slot_y<DT>(ly + 1, xch), z1 = slot_z<DT>(lz + 1, xch);
+    return trilerp(Vox<DT>::dec(base[z0 + y0 + x0]), Vox<DT>::dec(base[z0 + y0 + x1]),
+                   Vox<DT>::dec(base[z0 + y1 + x0]), Vox<DT>::dec(base[z0 + y1 + x1]),
+                   Vox<DT>::dec(base[z1 + y0 + x0]), Vox<DT>::dec(base[z1 + y0 + x1]),
+                   Vox<DT>::dec(base[z1 + y1 + x0]), Vox<DT>::dec(base[z1 + y1 + x1]), w0, w1, w2);
+}
+
+// Value of global voxel position (gx, gy, gz) (floor indices) from the pool.
+template <int DT, int INTERP>
+__device__ __forceinline__ float pool_value(const DevCube& c, int gx, int gy, int gz, float w0,
+                                            float w1, float w2) {
+    const uint32_t slot = __umul24(__umul24(gz >> 5, c.by) + (gy >> 5), c.bx) + (gx >> 5);
+    const typename Vox<DT>::T* base = (const typename Vox<DT>::T*)(c.pool + (uint64_t)slot * c.stride);
+    return slot_value<DT, INTERP>(base, c.xch, gx & 31, gy & 31, gz & 31, w0, w1, w2);
+}
+
+// The 8 trilinear corners at element idx of a box staged in LDS (strides 1,
+// sy, sz elements), decoded to float.  16-bit storage: each pair (x, x+1) is
+// cut from the two aligned dwords that hold it (row strides are multiples of
+// 8 elements, so every row shares the parity of idx), keeping every LDS
+// access dword-aligned.
+template <int DT>
+__device__ __forceinline__ void box_corners(__attribute__((address_space(3))) const typename Vox<DT>::T* box,
+                                            int idx, int sy, int sz, float c[8]) {
+    if (DT == 0) {
+        const auto* bp = box + idx;
+        c[0] = Vox<DT>::dec(bp[0]);
+        c[1] = Vox<DT>::dec(bp[1]);
+        c[2] = Vox<DT>::dec(bp[sy]);
+        c[3] = Vox<DT>::dec(bp[sy + 1]);
+        c[4] = Vox<DT>::dec(bp[sz]);
+        c[5] = Vox<DT>::dec(bp[sz + 1]);
+        c[6] = Vox<DT>::dec(bp[sz + sy]);
+        c[7] = Vox<DT>::dec(bp[sz + sy + 1]);
+        return;
+    }
+    typedef __attribute__((address_space(3))) const uint32_t LW;
+    LW* wp = (LW*)box + (idx >> 1);
+    const uint32_t sel = (idx & 1) ? 0x05040302u : 0x03020100u;
+    const int hy = sy >> 1, hz = sz >> 1;
+    const uint32_t p00 = __builtin_amdgcn_perm(wp[1], wp[0], sel);
+    const uint32_t p10 = __builtin_amdgcn_perm(wp[hy + 1], wp[hy], sel);
+    const uint32_t p01 = __builtin_amdgcn_perm(wp[hz + 1], wp[hz], sel);
+    const uint32_t p11 = __builtin_amdgcn_perm(wp[hz + hy + 1], wp[hz + hy], sel);
+    c[0] = Vox<DT>::dec((uint16_t)p00);
+    c[1] = Vox<DT>::dec((uint16_t)(p00 >> 16));
+    c[2] = Vox<DT>::dec((uint16_t)p10);
+    c[3] = Vox<DT>::dec((uint16_t)(p10 >> 16));
+    c[4] = Vox<DT>::dec((uint16_t)p01);
+    c[5] = Vox<DT>::dec((uint16_t)(p01 >> 16));
+    c[6] = Vox<DT>::dec((uint16_t)p11);
+    c[7] = Vox<DT>::dec((uint16_t)(p11 >> 16));
+}
+
+// Accumulation state of one ray.
+struct Accum {
+    float C0, C1, C2, T, m;
+};
+
+// Classify sample value v and composite it front to back; returns true when
+// the ray becomes opaque enough to stop.
+__device__ __forceinline__ bool composite(const DevReq& R, const float* __restrict__ tfl, float v,
+                                          bool last, const Ray& ray, Accum& acc) {
+    if (v < R.tf.clip) return false;  // opacity factor 1, weight 0: no change
+    float u = __builtin_fmaf(v, R.tf.scale, R.tf.bias);
+    u = __builtin_amdgcn_fmed3f(u, 0.0f, (float)(R.tf.n - 1));
+    // u >= 0: truncation is the floor; at u = n - 1 the last row is taken with
+    // weight 0 (its difference entry is zero), which gives that row exactly
+    const float g = __builtin_amdgcn_fractf(u);
+    const float4* row = (const float4*)(tfl + 8 * (int)u);
+    const float4 r0 = row[0], dr = row[1];
+    float kap = __builtin_fmaf(g, dr.w, r0.w);
+    kap = v < R.tf.clip ? 0.0f : kap;
+    // emission-absorption over the segment: alpha = 1 - exp(-kappa len)
+    const float ex = __builtin_amdgcn_exp2f(kap * (last ? ray.c_last : ray.c_full));
+    const float wgt = acc.T * (1.0f - ex);
+    acc.C0 = __builtin_fmaf(wgt, __builtin_fmaf(g, dr.x, r0.x), acc.C0);
+    acc.C1 = __builtin_fmaf(wgt, __builtin_fmaf(g, dr.y, r0.y), acc.C1);
+    acc.C2 = __builtin_fmaf(wgt, __builtin_fmaf(g, dr.z, r0.z), acc.C2);
+    acc.T *= ex;
+    return acc.T <= R.ert_T;
+}
+
+// Two consecutive samples of one ray, composited as composite() would one
+// after the other, without a branch between them: once the first makes the
+// ray opaque enough to stop, the second enters with opacity factor 1 and
+// weight 0, which leaves colour and transmittance exactly as they were.
+// nexec counts the samples composited; returns true when the ray stops.
+__device__ __forceinline__ bool composite2(const DevReq& R, const float* __restrict__ tfl, float v0,
+                                           float v1, bool last1, const Ray& ray, Accum& acc,
+                                           unsigned& nexec) {
+    // Below the clip a sample has opacity factor exactly 1 and weight 0 and
+    // changes nothing: the table rows are read only for lanes that need them.
+    if (v0 < R.tf.clip && v1 < R.tf.clip) {
+        nexec += 2u;
+        return false;
+    }
+    const float hi = (float)(R.tf.n - 1);
+    const float u0 = __builtin_amdgcn_fmed3f(__builtin_fmaf(v0, R.tf.scale, R.tf.bias), 0.0f, hi);
+    const float u1 = __builtin_amdgcn_fmed3f(__builtin_fmaf(v1, R.tf.scale, R.tf.bias), 0.0f, hi);
+    const float g0 = __builtin_amdgcn_fractf(u0), g1 = __builtin_amdgcn_fractf(u1);
+    const float4* ra = (const float4*)(tfl + 8 * (int)u0);
+    const float4* rb = (const float4*)(tfl + 8 * (int)u1);
+    const float4 a0 = ra[0], da = ra[1], b0 = rb[0], db = rb[1];
+    float k0 = __builtin_fmaf(g0, da.w, a0.w);
+    float k1 = __builtin_fmaf(g1, db.w, b0.w);
+    k0 = v0 < R.tf.clip ? 0.0f : k0;
+    k1 = v1 < R.tf.clip ? 0.0f : k1;
+    const float e0 = __builtin_amdgcn_exp2f(k0 * ray.c_full);
+    const float e1r = __builtin_amdgcn_exp2f(k1 * (last1 ? ray.c_last : ray.c_full));
+    const float w0 = acc.T * (1.0f - e0);
+    acc.C0 = __builtin_fmaf(w0, __builtin_fmaf(g0, da.x, a0.x), acc.C0);
+    acc.C1 = __builtin_fmaf(w0, __builtin_fmaf(g0, da.y, a0.y), acc.C1);
+    acc.C2 = __builtin_fmaf(w0, __builtin_fmaf(g0, da.z, a0.z), acc.C2);
+    const float T0 = acc.T * e0;
+    const bool go = T0 > R.ert_T;
+    const float e1 = go ? e1r : 1.0f;
+    const float w1 = T0 * (1.0f - e1);
+    acc.C0 = __builtin_fmaf(w1, __builtin_fmaf(g1, db.x, b0.x), acc.C0);
+    acc.C1 = __builtin_fmaf(w1, __builtin_fmaf(g1, db.y, b0.y), acc.C1);
+    acc.C2 = __builtin_fmaf(w1, __builtin_fmaf(g1, db.z, b0.z), acc.C2);
+    acc.T = T0 * e1;
+    nexec += go ? 2u : 1u;
+    return acc.T <= R.ert_T;
+}
+
+template <int MODE>
+__device__ __forceinline__ void store_pixel(const DevReq& R, int px, int py, bool hit,
+                                            const Accum& acc) {
+    const int64_t pix = (int64_t)py * R.W + px;
+    if (MODE == 0) {
+        *(float4*)(R.out + 4 * pix) =
+            hit ? make_float4(acc.C0, acc.C1, acc.C2, 1.0f - acc.T) : make_float4(0.f, 0.f, 0.f, 0.f);
+    } else {
+        R.out[pix] = hit ? ((acc.m >= R.tf.clip) ? acc.m * R.out_scale : 0.0f) : -VR_INF;
+    }
+}
+
+__device__ __forceinline__ void tile_pixel(const DevReq& R, int tx, int ty, int& px, int& py) {
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    px = tx * VR_TW + (wave & 3) * 8 + (lane & 7);
+    py = ty * VR_TH + (wave >> 2) * 8 + (lane >> 3);
+}
+
+// ---------------------------------------------------------------------------
+// Per-ray brick walker (used when the rays of a tile diverge too much to
+// share a slab axis, e.g. tiny images with a wide field of view).  Positions
+// are anchored in float-float at every brick entry and advanced in float in
+// brick-local coordinates; empty 8^3 cells are jumped over.
+// ---------------------------------------------------------------------------
+template <int MODE, int DT, int INTERP>
+__device__ __forceinline__ void render_lane_direct(const DevReq& R, const int px, const int py,
+                                                   const float* __restrict__ tfl, LaneCounts& cnt) {
+    typedef typename Vox<DT>::T VT;
+    Ray ray;
+    ray_setup(R, px, py, ray);
+    const int n = ray.n;
+    Accum acc = {0.0f, 0.0f, 0.0f, 1.0f, -VR_INF};
+    if (n == 0) {
+        store_pixel<MODE>(R, px, py, false, acc);
+        return;
+    }
+    const int N[3] = {R.cube.nx, R.cube.ny, R.cube.nz};
+    const int B[3] = {R.cube.bx, R.cube.by, R.cube.bz};
+    float inv_dd[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) inv_dd[a] = ray.dd[a] != 0.0f ? 1.0f / ray.dd[a] : 0.0f;
+    const float shift = INTERP == 0 ? 0.5f : 0.0f;
+    int k0 = 0, m = 0, j = 0;
+    float A[3] = {0.0f, 0.0f, 0.0f}, hb[3] = {0.0f, 0.0f, 0.0f};
+    const uint8_t* base = nullptr;
+    uint64_t mask = 0;
+    unsigned nexec = 0, nskip = 0;
+    bool stopped = false;
+    while (true) {
+        if (j >= m) {
+            k0 += m;
+            if (k0 >= n) break;
+            const ff t = sample_t(R, ray, k0);
+            int b[3];
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                const ff P = ff_add(ray.o[a], ff_mul(t, ray.d[a]));
+                int bb = (int)floorf(P.hi * (1.0f / VR_BRICK));
+                bb = bb < 0 ? 0 : (bb > B[a] - 1 ? B[a] - 1 : bb);
+                b[a] = bb;
+                A[a] = ff_to_f(ff_add(P, ff_make(-(float)(VR_BRICK * bb))));
+                hb[a] = fminf(31.999998f, (float)(N[a] - 1 - VR_BRICK * bb));
+            }
+            float s = VR_INF;
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                if (ray.dd[a] > 0.0f && b[a] < B[a] - 1)
+                    s = fminf(s, ((float)VR_BRICK - A[a]) * inv_dd[a]);
+                if (ray.dd[a] < 0.0f && b[a] > 0) s = fminf(s, (-A[a]) * inv_dd[a]);
+            }
+            const int rem = n - k0;
+            m = s >= (float)rem ? rem : max(1, (int)ceilf(s));
+            j = 0;
+            const uint64_t slot = ((uint64_t)b[2] * B[1] + b[1]) * B[0] + b[0];
+            base = R.cube.pool + slot * R.cube.stride;
+            mask = R.use_skip ? R.cube.mask[slot] : ~0ull;
+            if (mask == 0) {
+                nskip += m;
+                j = m;
+                continue;
+            }
+        }
+        const bool last = (k0 + j == n - 1);
+        const float jf = (float)j + ((last && j > 0) ? ray.last_adj : 0.0f);
+        const float p0 = __builtin_fmaf(jf, ray.dd[0], A[0]);
+        const float p1 = __builtin_fmaf(jf, ray.dd[1], A[1]);
+        const float p2 = __builtin_fmaf(jf, ray.dd[2], A[2]);
+        const float q0 = __builtin_amdgcn_fmed3f(p0, 0.0f, hb[0]);
+        const float q1 = __builtin_amdgcn_fmed3f(p1, 0.0f, hb[1]);
+        const float q2 = __builtin_amdgcn_fmed3f(p2, 0.0f, hb[2]);
+        int i0, i1, i2, cell;
+        float w0 = 0.0f, w1 = 0.0f, w2 = 0.0f;
+        if (INTERP == 1) {
+            const float f0 = floorf(q0), f1 = floorf(q1), f2 = floorf(q2);
+            w0 = q0 - f0;
+            w1 = q1 - f1;
+            w2 = q2 - f2;
+            i0 = (int)f0;
+            i1 = (int)f1;
+            i2 = (int)f2;
+            cell = (i0 >> 3) | ((i1 >> 3) << 2) | ((i2 >> 3) << 4);
+        } else {
+            i0 = (int)floorf(q0 + 0.5f);
+            i1 = (int)floorf(q1 + 0.5f);
+            i2 = (int)floorf(q2 + 0.5f);
+            cell = (min(i0, 31) >> 3) | ((min(i1, 31) >> 3) << 2) | ((min(i2, 31) >> 3) << 4);
+        }
+        if (!((mask >> cell) & 1ull)) {
+            // jump to the first sample past this cell, pulling the cell's faces in by
+            // 1e-4 voxel so rounding can never skip a sample of the next cell
+            const int c3[3] = {cell & 3, (cell >> 2) & 3, cell >> 4};
+            const float pw[3] = {p0 + shift, p1 + shift, p2 + shift};
+            float s = VR_INF;
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                if (ray.dd[a] > 0.0f)
+                    s = fminf(s, ((float)(VR_CELL * (c3[a] + 1)) - 1e-4f - pw[a]) * inv_dd[a]);
+                else if (ray.dd[a] < 0.0f)
+                    s = fminf(s, ((float)(VR_CELL * c3[a]) + 1e-4f - pw[a]) * inv_dd[a]);
+            }
+            const int jump = s >= 1.0e6f ? (1 << 20) : max(1, (int)ceilf(s));
+            nskip += min(jump, m - j);
+            j += jump;
+            continue;
+        }
+        const float v = slot_value<DT, INTERP>((const VT*)base, R.cube.xch, i0, i1, i2, w0, w1, w2);
+        ++nexec;
+        ++j;
+        if (MODE == 1) {
+            acc.m = fmaxf(acc.m, v);
+            continue;
+        }
+        if (composite(R, tfl, v, last, ray, acc)) {
+            stopped = true;
+            break;
+        }
+    }
+    store_pixel<MODE>(R, px, py, true, acc);
+    cnt.nominal += (unsigned)n;
+    cnt.exec += nexec;
+    cnt.hit += 1u;
+    cnt.ert += stopped ? 1u : 0u;
+    cnt.skipped += nskip;
+}
+
+// ---------------------------------------------------------------------------
+// Slab-staged tile renderer (the main path).
+//
+// A 512-thread workgroup owns a 32x16 pixel tile and marches all its rays in
+// lock-step through slabs along the major axis M of the tile's view direction,
+// front to back.  Every ray of the tile passes, at any plane perpendicular to
+// M, inside the quadrilateral cut by the tile's four corner rays (the tile's
+// rays form a pyramid, or a prism for orthographic views), so the box of voxel
+// indices the samples of a slab can touch follows from the corner rays alone.
+// Each slab is the thickest (up to 32 voxels, and at most twice the previous
+// one) whose box fits twice a fixed reference size; that choice depends only
+// on the tile's geometry, so the image never depends on staging decisions,
+// batch composition or the LDS the caller leaves free.  The box's 8^3 cells
+// are tested against the skip grid two slabs ahead, the next slab's box is
+// copied into LDS with 16-byte global->LDS loads once the current slab has
+// been sampled, and every lane interpolates its ray's samples of the slab
+// from LDS, skipping runs of 8 samples whose cells are all inactive where few
+// cells are active.  A box larger than its buffer is sampled straight from
+// the brick pool with the same arithmetic.
+// ---------------------------------------------------------------------------
+#define VR_BIG 0x3fffffff
+#define VR_SMAX 32
+// boxes are sized against this many bytes whatever LDS is actually free
+#define VR_BOX_REF 73728
+
+
+__device__ __forceinline__ int wave_min(int v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = min(v, __shfl_xor(v, o));
+    return v;
+}
+__device__ __forceinline__ int wave_max(int v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = max(v, __shfl_xor(v, o));
+    return v;
+}
+
+// Voxel index and weights of a position in box-local coordinates: clamped to
+// [0, hi] (the cube's last voxel on the upper side; the box never starts below
+// a sample), so truncation is the floor.  Trilinear at q = N - 1 takes the last
+// voxel with weight 0 (its +1 neighbour is the edge-clamped apron).
+template <int INTERP>
+__device__ __forceinline__ void floor_idx(const float p[3], const float hi[3], int i[3], float w[3]) {
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const float q = __builtin_amdgcn_fmed3f(p[a], 0.0f, hi[a]);
+        if (INTERP == 1) {
+            w[a] = __builtin_amdgcn_fractf(q);
+            i[a] = (int)q;
+        } else {
+            w[a] = 0.0f;
+            i[a] = (int)(q + 0.5f);
+        }
+    }
+}
+
+// exact i / d for 0 <= i < 2^22 and 0 < d < 2^22 via a float reciprocal
+__device__ __forceinline__ int div_small(int i, int d, float inv_d) {
+    int q = (int)((float)i * inv_d);
+    q -= q * d > i ? 1 : 0;
+    q += (q + 1) * d <= i ? 1 : 0;
+    return q;
+}
+
+// The tile's corner rays as lines over the major axis: on the plane M = z the
+// corner ray k sits at lateral coordinate c[k][q] + z * r[k][q] (q = 0 for axis
+// (M+1)%3, 1 for (M+2)%3).
+struct Corners {
+    float c[4][2], r[4][2];
+};
+
+// LDS elements per z plane of a box: np chunks per row and d1 rows.  Rows
+// start 16-byte aligned (odd np spreads them over the LDS banks four dwords
+// apart).  When M is x, the lanes of a wave read at nearly the same x and
+// differ in y and z, which leaves them few bank groups; one dword more per
+// plane (global->LDS loads accept dword-aligned LDS addresses) spreads them
+// over all banks.
+template <int M, int CV>
+__device__ __forceinline__ int box_skew() {
+    return M == 0 ? CV / 4 : 0;
+}
+template <int M, int CV>
+__device__ __forceinline__ int box_plane(int np, int d1) {
+    return np * CV * d1 + box_skew<M, CV>();
+}
+
+// One slab: planes [z0, z0 + S] along M, and the box of voxel indices its
+// samples can touch (floor indices plus the +1 neighbour), clamped to the cube.
+struct Slab {
+    int z0, S;
+    int lo[3], dim[3];
+    int xa, nc;   // first 16-byte-aligned x of the box, 16-byte chunks of data per box row
+    int np;       // chunks per LDS row: nc, rounded up to odd from 3 chunks on so
+                  // that consecutive rows start on different LDS banks
+    int elems;    // LDS elements of the box (row pitch np * chunk), 0 if empty
+    int big;      // the box takes both LDS buffers
+    int boff;     // byte offset of the box in the LDS box area
+    int late;     // copied only after the previous slab is sampled (it or the
+                  // previous slab takes both buffers)
+};
+
+template <bool B>
+struct BoolC {
+    static constexpr bool value = B;
+};
+
+// skip-grid rows of a slab box kept in LDS for the waves' own checks
+#define VR_CROW 128
+
+struct TileShared {
+    int red[4];         // tile-start reductions: first/last sample planes
+    int any[8];         // slab k may contribute (skip grid), ring by k % 8
+    unsigned nact[8];   // active cells of slab k's box (2^20 and up: rows not kept), ring by k % 8
+    int alive[3];       // some ray still marching after slab k, ring by k % 3
+    Slab ring[4];       // slab k's geometry, ring by k % 4 (S == 0: no such slab)
+    uint64_t crow[3][VR_CROW];  // slab k's cell rows (bit i: cell c0x + i), ring by k % 3
+};
+
+template <int M, int CV>
+__device__ __forceinline__ Slab slab_box(int z0, int S, const Corners& cr, const int N[3],
+                                         int zmin, int zmax) {
+    constexpr int A1 = (M + 1) % 3, A2 = (M + 2) % 3;
+    Slab s;
+    s.z0 = z0;
+    s.S = S;
+    // samples of the slab lie on [z0, z0 + S] along M up to rounding; at the
+    // cube's faces they can also lie in [-1/2, 0) or (N - 1, N - 1/2]
+    float za = z0 <= 0 ? -0.5f : (float)z0;
+    float zb = z0 + S >= N[M] - 1 ? (float)N[M] - 0.5f : (float)(z0 + S);
+    za -= 1e-3f;
+    zb += 1e-3f;
+    int lo[3], hi[3];
+    lo[M] = max(max(z0 - 1, zmin - 1), 0);
+    hi[M] = min(min(z0 + S, zmax + 1), N[M] - 1);
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+        const int a = q == 0 ? A1 : A2;
+        float mn = VR_INF, mx = -VR_INF;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const float v0 = __builtin_fmaf(za, cr.r[k][q], cr.c[k][q]);
+            const float v1 = __builtin_fmaf(zb, cr.r[k][q], cr.c[k][q]);
+            mn = fminf(mn, fminf(v0, v1));
+            mx = fmaxf(mx, fmaxf(v0, v1));
+        }
+        lo[a] = max((int)floorf(mn - 0.01f), 0);
+        hi[a] = min((int)floorf(mx + 0.01f), N[a] - 1);
+    }
+    bool empty = false;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        s.lo[a] = lo[a];
+        s.dim[a] = hi[a] - lo[a] + 2;
+        empty = empty || hi[a] < lo[a];
+    }
+    s.xa = lo[0] & ~(CV - 1);
+    s.nc = (lo[0] + s.dim[0] - 1 - s.xa) / CV + 1;
+    s.np = s.nc >= 3 ? (s.nc | 1) : s.nc;
+    s.big = 0;
+    s.boff = 0;
+    s.late = 0;
+    s.elems = empty ? 0 : box_plane<M, CV>(s.np, s.dim[1]) * s.dim[2];
+    return s;
+}
+
+// Thickest slab entered at plane ze, at most hi voxels, whose box holds at
+// most cap elements (bisection: the box only grows with the thickness);
+// ok = false when not even one voxel fits.
+template <int M, int CV>
+__device__ __forceinline__ Slab fit_slab(int ze, int sgn, int hi, int cap, const Corners& cr,
+                                         const int N[3], int zmin, int zmax, bool& ok) {
+    Slab best = slab_box<M, CV>(sgn > 0 ? ze : ze - hi, hi, cr, N, zmin, zmax);
+    ok = true;
+    if (best.elems <= cap) return best;
+    int lo = 0;  // thickest known to fit (0: none); hi never fits
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        const Slab m = slab_box<M, CV>(sgn > 0 ? ze : ze - mid, mid, cr, N, zmin, zmax);
+        if (m.elems <= cap) {
+            lo = mid;
+            best = m;
+        } else {
+            hi = mid;
+        }
+    }
+    ok = lo > 0;
+    return best;
+}
+
+// Next slab entered at plane ze: the thickest (at most twice the previous
+// thickness and VR_SMAX) whose box fits both LDS buffers of the reference
+// size.  Such a box is copied only after the slab before it has been sampled;
+// measured on the full-size workload, slabs twice as thick beat overlapping
+// the copy of a one-buffer box with the sampling of the previous slab.  A box
+// that does not fit even one voxel thick is marched 8 voxels at a time from
+// the brick pool.  Only geometry decides, never the LDS a launch actually has.
+template <int M, int CV, int ELEM>
+__device__ __forceinline__ Slab next_slab(int ze, int sgn, int Sprev, const Corners& cr,
+                                          const int N[3], int zmin, int zmax) {
+    constexpr int cap = VR_BOX_REF / ELEM;
+    bool ok;
+    Slab b = fit_slab<M, CV>(ze, sgn, min(VR_SMAX, 2 * Sprev), 2 * cap, cr, N, zmin, zmax, ok);
+    if (ok) {
+        b.big = 1;
+        return b;
+    }
+    return slab_box<M, CV>(sgn > 0 ? ze : ze - 8, 8, cr, N, zmin, zmax);
+}
+
+// Anchor of lattice sample k0 (without the last segment's shift) relative to
+// the integer point lo on one axis: E + (k0 + 1/2) step d - lo, with E the
+// ray's entry point, evaluated in float-float and rounded once.
+__device__ __forceinline__ float anchor_axis(const ff& E, const ff& d, const ff& sk, int lo) {
+#pragma clang fp contract(off)
+    ff h = two_sum(E.hi, -(float)lo);
+    h.lo += E.lo;
+    const ff p = ff_mul(sk, d);
+    const ff q = two_sum(h.hi, p.hi);
+    return q.hi + (q.lo + (h.lo + p.lo));
+}
+
+template <int MODE, int DT, int INTERP, int M>
+__device__ __forceinline__ bool tile_march(const DevReq& R, const Ray& ray, const int px,
+                                           const int py, const bool inimg, const Corners& cr,
+                                           const int sgn, const float* __restrict__ tfl,
+                                           uint8_t* __restrict__ boxes, TileShared& sh,
+                                           LaneCounts& cnt) {
+    typedef typename Vox<DT>::T VT;
+    typedef __attribute__((address_space(3))) const VT LVT;
+    constexpr int ELEM = DT == 0 ? 4 : 2;
+    constexpr int CV = 16 / ELEM;
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    const int N[3] = {R.cube.nx, R.cube.ny, R.cube.nz};
+    const int cap = R.box_bytes / ELEM;
+    const bool act = ray.n > 0;
+
+    // ---- tile-wide range of sample planes along M -----------------------------
+    int zf = 0, zl = 0;
+    ff E[3];
+    if (act) {
+        const ff t1 = sample_t(R, ray, ray.n - 1);
+        const ff t0 = sample_t(R, ray, 0);
+#pragma unroll
+        for (int a = 0; a < 3; ++a) E[a] = ff_add(ray.o[a], ff_mul(ray.tin, ray.d[a]));
+        const float pf = ff_to_f(ff_add(ray.o[M], ff_mul(t0, ray.d[M])));
+        const float pl = ff_to_f(ff_add(ray.o[M], ff_mul(t1, ray.d[M])));
+        const float hm = (float)(N[M] - 1);
+        zf = (int)floorf(fminf(fmaxf(pf, 0.0f), hm));
+        zl = (int)floorf(fminf(fmaxf(pl, 0.0f), hm));
+    } else {
+#pragma unroll
+        for (int a = 0; a < 3; ++a) E[a] = ff_make(0.0f);
+    }
+    {
+        const int a = wave_min(act ? min(zf, zl) : VR_BIG);
+        const int b = wave_max(act ? max(zf, zl) : -VR_BIG);
+        if (lane == 0) {
+            atomicMin(&sh.red[0], a);
+            atomicMax(&sh.red[1], b);
+        }
+    }
+    __syncthreads();
+    int zmin = sh.red[0], zmax = sh.red[1];
+    if (zmin == VR_BIG) {  // no ray of the tile meets the cube: no slab
+        zmin = 0;
+        zmax = -1;
+    }
+    // planes: marching up, slabs start at zmin and go while the entry plane is
+    // <= zmax; marching down, they start at zmax + 1 and go while entry > zmin
+    auto slab_exists = [&](int ze) { return sgn > 0 ? ze <= zmax : ze > zmin; };
+    auto exit_plane = [&](const Slab& s) { return sgn > 0 ? s.z0 + s.S : s.z0; };
+    // wave 0 lays out the slabs (identical in every lane) and publishes them
+    // Buffers: a one-buffer box goes to the buffer the previous slab does not
+    // use; a two-buffer box, and any box after one, is copied late.
+    Slab w0 = {};
+    bool w0_first = true;
+    int w0_buf = 1;
+    auto produce = [&](int slot) {
+        Slab s = {};
+        if (w0_first) {
+            const int ze = sgn > 0 ? zmin : zmax + 1;
+            if (slab_exists(ze)) s = next_slab<M, CV, ELEM>(ze, sgn, VR_SMAX, cr, N, zmin, zmax);
+        } else if (w0.S != 0 && slab_exists(exit_plane(w0))) {
+            s = next_slab<M, CV, ELEM>(exit_plane(w0), sgn, w0.S, cr, N, zmin, zmax);
+        }
+        if (s.S != 0) {
+            const int buf = (s.big || w0.big) ? 0 : 1 - w0_buf;
+            s.boff = buf * R.box_bytes;
+            s.late = (!w0_first && (s.big || w0.big)) ? 1 : 0;
+            w0_buf = buf;
+        }
+        w0_first = false;
+        if (lane == 0) sh.ring[slot] = s;
+        w0 = s;
+    };
+
+    // ---- per-ray state --------------------------------------------------------------
+    const float om = act ? ff_to_f(ray.o[M]) : 0.0f;
+    const float inv_dm = act ? 1.0f / ray.d[M].hi : 0.0f;
+    const float tinf = act ? ff_to_f(ray.tin) : 0.0f;
+    const float inv_step = 1.0f / ff_to_f(R.step);
+    Accum acc = {0.0f, 0.0f, 0.0f, 1.0f, -VR_INF};
+    unsigned nexec = 0, nskip = 0;
+    bool stopped = false;
+    // first sample past the exit plane of a slab
+    auto slab_end = [&](const Slab& s, int kprev) -> int {
+        if (!act || stopped || s.S == 0) return kprev;
+        const int zx = exit_plane(s);
+        if (sgn > 0 ? zx > zl : zx <= zl) return ray.n;
+        const float kf = ceilf((((float)zx - om) * inv_dm - tinf) * inv_step - 0.5f);
+        return kf < (float)kprev ? kprev : (kf > (float)ray.n ? ray.n : (int)kf);
+    };
+    // Skip-grid words of a slab's cells: bits_issue loads them (one row of cells
+    // along x per thread); bits_done, once they have landed, marks the slab as
+    // possibly contributing and keeps rows of up to 64 cells in LDS (slabs of at
+    // most VR_CROW rows) for the finer per-wave checks during sampling.
+    const int Cx = 4 * R.cube.bx, Cy = 4 * R.cube.by;
+    struct Bits {
+        uint32_t w0, w1, m0, m1;
+        int lob, row;  // first bit in word w0; LDS row this thread keeps (-1: none)
+        int wide;      // treated as active; the slab's rows are not kept
+        int nofine;    // the slab's rows are not kept
+    };
+    auto bits_issue = [&](const Slab& s) -> Bits {
+        Bits b = {0u, 0u, 0u, 0u, 0, -1, 0, 0};
+        if (s.S == 0 || s.elems == 0) return b;
+        int c0[3], c1[3];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            c0[a] = s.lo[a] >> 3;
+            c1[a] = (s.lo[a] + s.dim[a] - 2) >> 3;
+        }
+        const int ny_ = c1[1] - c0[1] + 1, nrow = ny_ * (c1[2] - c0[2] + 1);
+        if (nrow > VR_WG) {
+            b.wide = tid == 0;  // more cell rows than threads: treated as active
+            return b;
+        }
+        b.nofine = (tid == 0 && nrow > VR_CROW) ? 1 : 0;
+        if (tid >= nrow) return b;
+        const int czr = div_small(tid, ny_, 1.0f / (float)ny_);
+        const int cy = c0[1] + tid - czr * ny_, cz = c0[2] + czr;
+        const int64_t b0 = ((int64_t)cz * Cy + cy) * Cx + c0[0];
+        const int64_t b1 = b0 + (c1[0] - c0[0]);
+        const int64_t wa = b0 >> 5, wb = b1 >> 5;
+        if (wb - wa > 1) {
+            b.wide = 1;  // more than two words: treated as active
+            return b;
+        }
+        const uint32_t lo_bit = (uint32_t)(b0 & 31), hi_bit = (uint32_t)(b1 & 31);
+        if (wa == wb) {
+            b.m0 = (hi_bit == 31 ? 0xffffffffu : ((1u << (hi_bit + 1)) - 1u)) & ~((1u << lo_bit) - 1u);
+        } else {
+            b.m0 = ~((1u << lo_bit) - 1u);
+            b.m1 = hi_bit == 31 ? 0xffffffffu : ((1u << (hi_bit + 1)) - 1u);
+            b.w1 = R.cube.cellbits[wb];
+        }
+        b.w0 = R.cube.cellbits[wa];
+        b.lob = (int)lo_bit;
+        b.row = nrow <= VR_CROW ? tid : -1;
+        return b;
+    };
+    auto bits_done = [&](int k, const Bits& b) {
+        const uint32_t lo = b.w0 & b.m0, hi = b.w1 & b.m1;
+        if (b.wide || lo || hi) sh.any[k & 7] = 1;
+        unsigned add = (b.wide || b.nofine) ? (1u << 20) : 0u;
+        if (b.row >= 0) {
+            const uint64_t r = ((((uint64_t)hi) << 32) | lo) >> b.lob;
+            sh.crow[k % 3][b.row] = r;
+            add += (unsigned)__popcll(r);
+        }
+        if (add) atomicAdd(&sh.nact[k & 7], add);
+    };
+    // Copy a slab's box into its LDS buffer: the box is row-major over
+    // [z][y][16-byte chunk] with np chunks per row and planes box_plane()
+    // elements apart, and global->LDS loads write 16 bytes per lane at
+    // consecutive LDS addresses, so each wave instruction moves rw = 64 / np
+    // whole rows, of one plane where planes are not contiguous (lane l: row
+    // l / np, chunk l % np; the x part of its source address stays fixed for
+    // the whole box).  Rows of more than 64 chunks go one row per instruction
+    // group.
+    auto staged = [&](const Slab& s) { return s.elems <= (s.big ? 2 * cap : cap); };
+    const uint32_t bstride = (uint32_t)R.cube.stride;
+    auto row_src = [&](const Slab& s, int iy, int iz) -> const uint8_t* {
+        const int gy = min(s.lo[1] + iy, N[1] - 1), gz = min(s.lo[2] + iz, N[2] - 1);
+        const uint32_t slot_yz = __umul24(__umul24(gz >> 5, R.cube.by) + (gy >> 5), R.cube.bx);
+        const uint32_t off = (uint32_t)(slot_y<DT>(gy & 31, R.cube.xch) + slot_z<DT>(gz & 31, R.cube.xch)) * ELEM;
+        return R.cube.pool + ((uint64_t)slot_yz * bstride + off);
+    };
+    auto chunk_off = [&](const Slab& s, int c) -> uint64_t {
+        const int x = s.xa + min(c, s.nc - 1) * CV;  // pad slots repeat the last chunk
+        const int bxb = min(x >> 5, R.cube.bx - 1);
+        return (uint64_t)bxb * bstride + (uint32_t)(((x - 32 * bxb) / CV) * 128);
+    };
+    auto box_dma = [&](const Slab& s) {
+        if (s.S == 0 || s.elems == 0 || !staged(s)) return;
+        uint8_t* buf = boxes + s.boff;
+        const int np = s.np, d1 = s.dim[1], d2 = s.dim[2];
+        const int plane_bytes = box_plane<M, CV>(np, d1) * ELEM;
+        if (np <= 64) {
+            const float inv_np = 1.0f / (float)np;
+            const int rw = div_small(64, np, inv_np);
+            const int lr = div_small(lane, np, inv_np);
+            const bool on = lr < rw;
+            const uint64_t xo = chunk_off(s, lane - lr * np);
+            if (box_skew<M, CV>() != 0) {
+                // planes apart: groups of rw rows of one plane, one instruction each
+                const int gpp = div_small(d1 + rw - 1, rw, 1.0f / (float)rw);  // groups per plane
+                const float inv_gpp = 1.0f / (float)gpp;
+                for (int q = wave; q < gpp * d2; q += VR_NWAVE) {
+                    const int iz = div_small(q, gpp, inv_gpp);
+                    const int y0 = (q - iz * gpp) * rw;
+                    if (on && y0 + lr < d1)
+                        __builtin_amdgcn_global_load_lds((const void*)(row_src(s, y0 + lr, iz) + xo),
+                                                         (__attribute__((address_space(3))) void*)(buf + iz * plane_bytes + y0 * np * 16),
+                                                         16, 0, 0);
+                }
+                return;
+            }
+            // contiguous planes: groups of rw consecutive rows, one instruction each
+            const int rows = d1 * d2;
+            const float inv_d1 = 1.0f / (float)d1;
+            const int rstep = VR_NWAVE * rw;
+            const int r_first = wave * rw + lr;
+            int iz = div_small(r_first, d1, inv_d1);
+            int iy = r_first - iz * d1;
+            const int dz = div_small(rstep, d1, inv_d1), dy = rstep - dz * d1;
+            for (int r0 = wave * rw; r0 < rows; r0 += rstep) {
+                if (on && r0 + lr < rows)
+                    __builtin_amdgcn_global_load_lds((const void*)(row_src(s, iy, iz) + xo),
+                                                     (__attribute__((address_space(3))) void*)(buf + r0 * np * 16),
+                                                     16, 0, 0);
+                iy += dy;
+                iz += dz;
+                if (iy >= d1) {
+                    iy -= d1;
+                    ++iz;
+                }
+            }
+        } else {
+            const int rows = d1 * d2;
+            const float inv_d1 = 1.0f / (float)d1;
+            for (int r = wave; r < rows; r += VR_NWAVE) {
+                const int iz = div_small(r, d1, inv_d1), iy = r - iz * d1;
+                const uint8_t* src = row_src(s, iy, iz);
+                for (int c0 = 0; c0 < np; c0 += 64) {
+                    if (c0 + lane < np)
+                        __builtin_amdgcn_global_load_lds((const void*)(src + chunk_off(s, c0 + lane)),
+                                                         (__attribute__((address_space(3))) void*)(buf + iz * plane_bytes + (iy * np + c0) * 16),
+                                                         16, 0, 0);
+                }
+            }
+        }
+    };
+
+    // ---- prologue: slabs 0 and 1 ------------------------------------------------------
+    if (wave == 0) {
+        produce(0);
+        produce(1);
+    }
+    __syncthreads();
+    Slab s0 = sh.ring[0], s1 = sh.ring[1];
+    int ks = 0, ke0 = slab_end(s0, 0);
+    if (R.use_skip) {
+        bits_done(0, bits_issue(s0));
+        bits_done(1, bits_issue(s1));
+        __syncthreads();
+    }
+    if (sh.any[0]) box_dma(s0);
+
+    // ---- slab pipeline -----------------------------------------------------------------
+    for (int it = 0; s0.S != 0; ++it) {
+        if (wave == 0) produce((it + 2) & 3);
+        if (tid == 0) {
+            sh.any[(it + 3) & 7] = R.use_skip ? 0 : 1;
+            sh.nact[(it + 3) & 7] = 0u;
+            sh.alive[it % 3] = 0;
+        }
+        __builtin_amdgcn_s_waitcnt(0);  // own box copies of slab it have landed
+        __syncthreads();
+        if (it > 0 && sh.alive[(it - 1) % 3] == 0) break;
+        const Slab s2 = sh.ring[(it + 2) & 3];
+        Bits bb = {0u, 0u, 0u, 0u, 0, -1, 0, 0};
+        if (R.use_skip) bb = bits_issue(s2);
+        if (!s1.late && sh.any[(it + 1) & 7]) box_dma(s1);
+        const int ke1 = slab_end(s1, ke0);
+        // ---- sample slab it
+        const int cnt_s = ke0 - ks;
+        if (cnt_s > 0 && !stopped) {
+            if (!sh.any[it & 7]) {
+                nskip += (unsigned)cnt_s;
+            } else {
+                float A[3], ch[3];
+                {
+                    const float kf = (float)ks + 0.5f;
+                    ff sk = two_prod(kf, R.step.hi);
+                    sk.lo = __builtin_fmaf(kf, R.step.lo, sk.lo);
+#pragma unroll
+                    for (int a = 0; a < 3; ++a) {
+                        A[a] = anchor_axis(E[a], ray.d[a], sk, s0.lo[a]);
+                        ch[a] = (float)(N[a] - 1 - s0.lo[a]);
+                    }
+                }
+                // samples are taken two at a time so that the second one's box
+                // reads are in flight while the first one is classified
+                auto value = [&](auto fetch, int j, bool last) {
+                    const float jf = (float)j + (last ? ray.last_adj : 0.0f);
+                    const float p[3] = {__builtin_fmaf(jf, ray.dd[0], A[0]),
+                                        __builtin_fmaf(jf, ray.dd[1], A[1]),
+                                        __builtin_fmaf(jf, ray.dd[2], A[2])};
+                    int i[3];
+                    float w[3];
+                    floor_idx<INTERP>(p, ch, i, w);
+                    return fetch(i, w);
+                };
+                // Finer skip where under a quarter of the box's cells are
+                // active: before every 8 samples each lane bounds the cells
+                // its samples j .. j+7 can touch (positions at j - 1/2, the
+                // last sample's earliest, and j + 7: per axis the clamped
+                // index is monotone in the position), and the wave passes
+                // over the 8 samples when no lane touches an active cell.
+                int cb0[3], cb1[3];
+#pragma unroll
+                for (int a = 0; a < 3; ++a) {
+                    cb0[a] = s0.lo[a] >> 3;
+                    cb1[a] = (s0.lo[a] + s0.dim[a] - 2) >> 3;
+                }
+                const int nyc = cb1[1] - cb0[1] + 1;
+                const unsigned ncell = (unsigned)((cb1[0] - cb0[0] + 1) * nyc * (cb1[2] - cb0[2] + 1));
+                const bool fine = R.use_skip && 4u * (unsigned)__builtin_amdgcn_readfirstlane((int)sh.nact[it & 7]) <= ncell;
+                const uint64_t* crow = sh.crow[it % 3];
+                auto live = [&](int j) -> bool {
+                    const float ja = (float)j - 0.5f, jb = (float)j + 7.0f;
+                    int c_lo[3], c_hi[3];
+#pragma unroll
+                    for (int a = 0; a < 3; ++a) {
+                        const float qa = __builtin_amdgcn_fmed3f(__builtin_fmaf(ja, ray.dd[a], A[a]), 0.0f, ch[a]);
+                        const float qb = __builtin_amdgcn_fmed3f(__builtin_fmaf(jb, ray.dd[a], A[a]), 0.0f, ch[a]);
+                        const int ia = INTERP == 1 ? (int)qa : (int)(qa + 0.5f);
+                        const int ib = INTERP == 1 ? (int)qb : (int)(qb + 0.5f);
+                        c_lo[a] = min(max((s0.lo[a] + min(ia, ib)) >> 3, cb0[a]), cb1[a]);
+                        c_hi[a] = min(max((s0.lo[a] + max(ia, ib)) >> 3, cb0[a]), cb1[a]);
+                    }
+                    const int nbx = c_hi[0] - c_lo[0] + 1;
+                    const uint64_t xm = (nbx >= 64 ? ~0ull : ((1ull << nbx) - 1ull)) << (c_lo[0] - cb0[0]);
+                    uint64_t hit = 0;
+                    for (int cz = c_lo[2]; cz <= c_hi[2]; ++cz)
+                        for (int cy = c_lo[1]; cy <= c_hi[1]; ++cy)
+                            hit |= crow[(cz - cb0[2]) * nyc + (cy - cb0[1])];
+                    return (hit & xm) != 0ull;
+                };
+                auto run = [&](auto fetch, auto chunked) {
+                    const int jl = ray.n - 1 - ks;  // index of the ray's last sample in this slab, if any
+                    int j = 0;
+                    for (; j + 1 < cnt_s; j += 2) {
+                        if (decltype(chunked)::value && (j & 7) == 0 && __ballot(live(j)) == 0ull) {
+                            nskip += (unsigned)min(8, cnt_s - j);
+                            j += 6;
+                            continue;
+                        }
+                        const float v0 = value(fetch, j, false);
+                        const float v1 = value(fetch, j + 1, j + 1 == jl);
+                        if (MODE == 1) {
+                            nexec += 2;
+                            acc.m = fmaxf(acc.m, fmaxf(v0, v1));
+                        } else if (composite2(R, tfl, v0, v1, j + 1 == jl, ray, acc, nexec)) {
+                            stopped = true;
+                            break;
+                        }
+                    }
+                    if (j < cnt_s && !stopped) {
+                        const float v = value(fetch, j, j == jl);
+                        ++nexec;
+                        if (MODE == 1) {
+                            acc.m = fmaxf(acc.m, v);
+                        } else if (composite(R, tfl, v, j == jl, ray, acc)) {
+                            stopped = true;
+                        }
+                    }
+                };
+                if (staged(s0)) {
+                    const LVT* box = (const LVT*)(boxes + s0.boff);
+                    const int pitch = s0.np * CV;
+                    const int sy = pitch, sz = box_plane<M, CV>(s0.np, s0.dim[1]);
+                    const int xoff = s0.lo[0] - s0.xa;
+                    // consecutive samples of a ray often share their cell: its
+                    // corners are read from LDS only when the cell changes (a
+                    // nearest sample's single read is cheaper than the test)
+                    int cidx = -1;
+                    float cc[8];
+                    auto fetch = [&](const int* i, const float* w) {
+                        const int idx = (int)__umul24(__umul24(i[2], s0.dim[1]) + i[1], pitch) + i[0] + xoff +
+                                        i[2] * box_skew<M, CV>();
+                        if (INTERP == 0) return Vox<DT>::dec(box[idx]);
+                        if (idx != cidx) {
+                            box_corners<DT>(box, idx, sy, sz, cc);
+                            cidx = idx;
+                        }
+                        return trilerp(cc[0], cc[1], cc[2], cc[3], cc[4], cc[5], cc[6], cc[7], w[0], w[1], w[2]);
+                    };
+                    if (fine)
+                        run(fetch, BoolC<true>());
+                    else
+                        run(fetch, BoolC<false>());
+                } else {
+                    auto fetch = [&](const int* i, const float* w) {
+                        return pool_value<DT, INTERP>(R.cube, s0.lo[0] + i[0], s0.lo[1] + i[1],
+                                                      s0.lo[2] + i[2], w[0], w[1], w[2]);
+                    };
+                    if (fine)
+                        run(fetch, BoolC<true>());
+                    else
+                        run(fetch, BoolC<false>());
+                }
+            }
+        }
+        if (R.use_skip) bits_done(it + 2, bb);
+        const bool done = !act || stopped || ke0 >= ray.n;
+        if (__ballot(!done) != 0ull && lane == 0) sh.alive[it % 3] = 1;
+        if (s1.late) {  // the box of slab it + 1 needs the LDS slab it used
+            __syncthreads();
+            if (sh.any[(it + 1) & 7]) box_dma(s1);
+        }
+        ks = ke0;
+        ke0 = ke1;
+        s0 = s1;
+        s1 = s2;
+    }
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+    if (inimg) store_pixel<MODE>(R, px, py, act, acc);
+    if (act) {
+        cnt.nominal += (unsigned)ray.n;
+        cnt.exec += nexec;
+        cnt.hit += 1u;
+        cnt.ert += stopped ? 1u : 0u;
+        cnt.skipped += nskip;
+    }
+    return true;
+}
+
+// Returns false (having rendered nothing) when the rays of the tile do not all
+// advance along one axis; the caller then runs the per-ray walker.
+template <int MODE, int DT, int INTERP>
+__device__ __forceinline__ bool render_tile(const DevReq& R, const int tx, const int ty,
+                                            const float* __restrict__ tfl,
+                                            uint8_t* __restrict__ boxes, TileShared& sh,
+                                            LaneCounts& cnt) {
+    const int tid = threadIdx.x;
+    int px, py;
+    tile_pixel(R, tx, ty, px, py);
+    const bool inimg = px < R.W && py < R.H;
+    if (tid == 0) {
+        sh.red[0] = VR_BIG;
+        sh.red[1] = -VR_BIG;
+        for (int q = 0; q < 8; ++q) {
+            sh.any[q] = R.use_skip ? 0 : 1;
+            sh.nact[q] = 0u;
+        }
+        sh.alive[0] = sh.alive[1] = sh.alive[2] = 0;
+    }
+    // tile centre ray fixes the major axis; the corner rays bound the tile's rays
+    ff oc[3], dc[3];
+    ray_dir(R.cam, (float)(tx * VR_TW) + 0.5f * VR_TW, (float)(ty * VR_TH) + 0.5f * VR_TH, oc, dc);
+    const float ad0 = fabsf(dc[0].hi), ad1 = fabsf(dc[1].hi), ad2 = fabsf(dc[2].hi);
+    const int m = (ad2 > ad0 && ad2 > ad1) ? 2 : (ad1 > ad0 ? 1 : 0);
+    const float dm = m == 0 ? dc[0].hi : (m == 1 ? dc[1].hi : dc[2].hi);
+    const int sgn = dm > 0.0f ? 1 : -1;
+    const int m1 = m == 2 ? 0 : m + 1, m2 = m == 0 ? 2 : m - 1;
+    Corners cr;
+    bool ok = true;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const float fi = (k & 1) ? (float)min(tx * VR_TW + VR_TW, R.W) - 0.5f : (float)(tx * VR_TW) + 0.5f;
+        const float fj = (k & 2) ? (float)min(ty * VR_TH + VR_TH, R.H) - 0.5f : (float)(ty * VR_TH) + 0.5f;
+        ff o[3], d[3];
+        ray_dir(R.cam, fi, fj, o, d);
+        const float o3[3] = {ff_to_f(o[0]), ff_to_f(o[1]), ff_to_f(o[2])};
+        const float d3[3] = {d[0].hi, d[1].hi, d[2].hi};
+        const float dmk = m == 0 ? d3[0] : (m == 1 ? d3[1] : d3[2]);
+        const float omk = m == 0 ? o3[0] : (m == 1 ? o3[1] : o3[2]);
+        ok = ok && (float)sgn * dmk >= 0.25f;
+        const float r1 = (m1 == 0 ? d3[0] : (m1 == 1 ? d3[1] : d3[2])) / dmk;
+        const float r2 = (m2 == 0 ? d3[0] : (m2 == 1 ? d3[1] : d3[2])) / dmk;
+        cr.r[k][0] = r1;
+        cr.r[k][1] = r2;
+        cr.c[k][0] = (m1 == 0 ? o3[0] : (m1 == 1 ? o3[1] : o3[2])) - omk * r1;
+        cr.c[k][1] = (m2 == 0 ? o3[0] : (m2 == 1 ? o3[1] : o3[2])) - omk * r2;
+    }
+    if (!ok) return false;
+    Ray ray;
+    ray.n = 0;
+    if (inimg) ray_setup(R, px, py, ray);
+    __syncthreads();
+    if (m == 0)
+        return tile_march<MODE, DT, INTERP, 0>(R, ray, px, py, inimg, cr, sgn, tfl, boxes, sh, cnt);
+    if (m == 1)
+        return tile_march<MODE, DT, INTERP, 1>(R, ray, px, py, inimg, cr, sgn, tfl, boxes, sh, cnt);
+    return tile_march<MODE, DT, INTERP, 2>(R, ray, px, py, inimg, cr, sgn, tfl, boxes, sh, cnt);
+}
+
+// One tile: slab-staged if possible, else one independent walker per ray.
+template <int MODE, int DT, int INTERP>
+__device__ __forceinline__ void render_tile_any(const DevReq& R, const int tx, const int ty,
+                                                const float* __restrict__ tfl,
+                                                uint8_t* __restrict__ boxes, TileShared& sh,
+                                                LaneCounts& cnt) {
+    if (render_tile<MODE, DT, INTERP>(R, tx, ty, tfl, boxes, sh, cnt)) return;
+    int px, py;
+    tile_pixel(R, tx, ty, px, py);
+    if (px < R.W && py < R.H) render_lane_direct<MODE, DT, INTERP>(R, px, py, tfl, cnt);
+}
+
+__device__ __forceinline__ void flush_counts(const LaneCounts& c, DevCounters* cnt,
+                                             unsigned* wg /* 5 LDS words */) {
+    atomicAdd(&wg[0], c.nominal);
+    atomicAdd(&wg[1], c.exec);
+    atomicAdd(&wg[2], c.hit);
+    atomicAdd(&wg[3], c.ert);
+    atomicAdd(&wg[4], c.skipped);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        atomicAdd(&cnt->samples_nominal, (unsigned long long)wg[0]);
+        atomicAdd(&cnt->samples_exec, (unsigned long long)wg[1]);
+        atomicAdd(&cnt->rays_hit, (unsigned long long)wg[2]);
+        atomicAdd(&cnt->rays_ert, (unsigned long long)wg[3]);
+        atomicAdd(&cnt->cells_skipped, (unsigned long long)wg[4]);
+    }
+}
+
+// dynamic LDS: transfer-function rows (n x 32 bytes), then two slab boxes
+template <int MODE, int DT, int INTERP>
+__global__ __launch_bounds__(VR_WG) void k_render(const DevReq R, const int* __restrict__ order,
+                                                   DevCounters* cnt) {
+    extern __shared__ float4 lds4[];
+    __shared__ unsigned wgc[5];
+    __shared__ TileShared sh;
+    float* tfl = (float*)lds4;
+    const int tf_bytes = MODE == 0 ? 32 * R.tf.n : 0;
+    if (MODE == 0) {
+        const float4* rows = (const float4*)R.tf.rows;
+        for (int e = threadIdx.x; e < 2 * R.tf.n; e += VR_WG) lds4[e] = rows[e];
+    }
+    if (cnt && threadIdx.x < 5) wgc[threadIdx.x] = 0u;
+    __syncthreads();
+    const int tile = order[blockIdx.x];
+    const int tx = tile % R.tiles_x, ty = tile / R.tiles_x;
+    LaneCounts c = {0u, 0u, 0u, 0u, 0u};
+    render_tile_any<MODE, DT, INTERP>(R, tx, ty, tfl, (uint8_t*)lds4 + tf_bytes, sh, c);
+    if (cnt) flush_counts(c, cnt, wgc);
+}
+
+
+// Static plus dynamic LDS of a launch must fit the workgroup's 160 KB.
+static inline hipError_t check_lds(const void* kernel, size_t dynamic_bytes) {
+    hipFuncAttributes a;
+    hipError_t e = hipFuncGetAttributes(&a, kernel);
+    if (e != hipSuccess) return e;
+    return a.sharedSizeBytes + dynamic_bytes <= (size_t)VR_LDS_MAX ? hipSuccess : hipErrorInvalidValue;
+}
+
+template <int MODE, int DT, int INTERP>
+static hipError_t launch_r(const DevReq& R, const int* order, DevCounters* cnt, hipStream_t s) {
+    const int grid = R.tiles_x * R.tiles_y;
+    const size_t lds = (MODE == 0 ? (size_t)R.tf.n * 32 : 0) + 2 * (size_t)R.box_bytes;
+    const hipError_t e = check_lds((const void*)k_render<MODE, DT, INTERP>, lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((k_render<MODE, DT, INTERP>), dim3(grid), dim3(VR_WG), lds, s, R, order, cnt);
+    return hipGetLastError();
+}
+
+// Defines the launcher of one (mode, storage) pair, both interpolations.
+#define VR_RENDER_LAUNCHER(MODE, DT)                                                          \
+    hipError_t vr_launch_render_##MODE##_##DT(const DevReq& R, const int* order,               \
+                                              DevCounters* cnt, hipStream_t s) {              \
+        return R.interp == 1 ? launch_r<MODE, DT, 1>(R, order, cnt, s)                         \
+                             : launch_r<MODE, DT, 0>(R, order, cnt, s);                        \
+    }

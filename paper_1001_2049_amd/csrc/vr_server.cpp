@@ -186,11 +186,10 @@ static void server_loop(Server* S) {
 }
 
 void server_stop(Ctx* c) {
-    Server* S = nullptr;
+    std::shared_ptr<Server> S;
     {
         std::lock_guard<std::mutex> g(c->server_mu);
-        S = c->server;
-        c->server = nullptr;
+        S.swap(c->server);
     }
     if (!S) return;
     {
@@ -208,12 +207,25 @@ void server_stop(Ctx* c) {
         if (sl.stream) (void)hipStreamDestroy(sl.stream);
     }
     // requests never completed (after a device error) still hold references
-    for (auto& kv : S->tickets)
-        if (!kv.second.done) drop_refs(c, kv.second.req);
-    delete S;
+    {
+        std::lock_guard<std::mutex> lk(S->m);
+        for (auto& kv : S->tickets) {
+            if (!kv.second.done) {
+                drop_refs(c, kv.second.req);
+                kv.second.done = true;
+                kv.second.status = VR_ESTATE;
+            }
+        }
+        if (S->fatal == VR_OK) {
+            S->fatal = VR_ESTATE;
+            S->fatal_msg = "server stopped";
+        }
+    }
+    S->cv_done.notify_all();
+    // callers still blocked in vr_wait hold their own reference to S
 }
 
-static Server* get_server(Ctx* c) {
+static std::shared_ptr<Server> get_server(Ctx* c) {
     std::lock_guard<std::mutex> g(c->server_mu);
     return c->server;
 }
@@ -267,9 +279,9 @@ vr_status vr_server_start(vr_ctx ctx, const vr_server_cfg* cfg) {
             }
             return st;
         }
-        Server* raw = S.release();
-        raw->th = std::thread(server_loop, raw);
-        c->server = raw;
+        std::shared_ptr<Server> sp(S.release());
+        sp->th = std::thread(server_loop, sp.get());
+        c->server = sp;
         return VR_OK;
     } catch (const std::exception& ex) {
         set_error(std::string("server start: ") + ex.what());
@@ -298,7 +310,7 @@ vr_status vr_submit(vr_ctx ctx, const vr_request* req, uint64_t* ticket) {
     }
     *ticket = 0;
     Ctx* c = (Ctx*)ctx;
-    Server* S = get_server(c);
+    std::shared_ptr<Server> S = get_server(c);
     if (!S) {
         set_error("server not running");
         return VR_ESTATE;
@@ -352,7 +364,7 @@ vr_status vr_poll(vr_ctx ctx, uint64_t ticket, int32_t* done) {
         return VR_EINVAL;
     }
     *done = 0;
-    Server* S = get_server((Ctx*)ctx);
+    std::shared_ptr<Server> S = get_server((Ctx*)ctx);
     if (!S) {
         set_error("server not running");
         return VR_ESTATE;
@@ -372,7 +384,7 @@ vr_status vr_wait(vr_ctx ctx, uint64_t ticket, double timeout_s, double* latency
         set_error("ctx is NULL");
         return VR_EINVAL;
     }
-    Server* S = get_server((Ctx*)ctx);
+    std::shared_ptr<Server> S = get_server((Ctx*)ctx);
     if (!S) {
         set_error("server not running");
         return VR_ESTATE;

@@ -16,7 +16,7 @@ import pytest
 
 import oracle
 import synth
-from gpu_common import TOL_F32, compare_ea, compare_mip, ref_render, wl_kwargs
+from gpu_common import TOL_F32, compare_ea, compare_mip, record, ref_render, wl_kwargs
 
 pytestmark = pytest.mark.gpu
 
@@ -66,8 +66,9 @@ def test_large_cube_sampled_pixels(large, mode):
     if mode == "ea":
         info = compare_ea(got, ref["values"], TOL_F32, ref["flags"])
     else:
-        info = compare_mip(got, ref["values"], TOL_F32, ref["flags"])
-    print("large %s %s stats=%s" % (mode, info, st))
+        info = compare_mip(got, ref["values"], TOL_F32, ref["flags"], ref.get("bounds"))
+    record("large f16 2048 %s sampled" % mode, info)
+    print("large %s stats=%s" % (mode, st))
     assert st["cells_skipped"] > 0 and st["samples_exec"] < st["samples_nominal"]
 
 

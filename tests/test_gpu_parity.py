@@ -1,6 +1,6 @@
 """GPU renderer vs the FP64 reference, element by element, through the C interface.
 
-Sizes span several 16x16 workgroup tiles, several 32^3 bricks and 8^3 skip
+Sizes span several 32x16-pixel workgroup tiles (512 threads), several 32^3 bricks and 8^3 skip
 cells, and ragged edges (image and cube sizes that are not multiples of the
 tile/brick/cell sizes).  Tolerances: max per-channel absolute error 1e-5 for
 float32 storage (RGBA in [0,1]); MIP values within 1e-5 * max(1, |m|);
@@ -16,7 +16,7 @@ import pytest
 
 import oracle
 import synth
-from gpu_common import TOL_F32, compare_ea, compare_mip, ref_render, set_state, wl_kwargs
+from gpu_common import TOL_F32, compare_ea, compare_mip, record, ref_render, set_state, wl_kwargs
 
 pytestmark = pytest.mark.gpu
 
@@ -76,7 +76,9 @@ def test_tiny_mip(R, tiny, tiny_cube, view, interp):
     set_state(R, wl, tf, cam)
     img = to_np(R.render(tiny_cube, W, H, mode="mip", interp=interp, step=wl.step))
     ref = ref_render(vol, wl_kwargs(wl, tf), cam, W, H, "mip", interp)
-    compare_mip(img, ref["image"], TOL_F32 if interp == "trilinear" else 0.0, ref["flags"])
+    info = compare_mip(img, ref["image"], TOL_F32 if interp == "trilinear" else 0.0, ref["flags"],
+                       ref.get("bounds"), clip=wl.clip_k * wl.cube.sigma)
+    record("tiny f32 %dx%d %s mip %s" % (W, H, view, interp), info)
 
 
 @pytest.mark.parametrize("view", ["z", "x", "orbit0", "orbit1", "orbit2"])
@@ -93,7 +95,7 @@ def test_tiny_ea(R, tiny, tiny_cube, view, ert):
     kw["ert"] = float(np.float32(ert))
     ref = ref_render(vol, kw, cam, W, H, "ea", "trilinear")
     info = compare_ea(img, ref["image"], TOL_F32, ref["flags"])
-    print(view, ert, info)
+    record("tiny f32 %dx%d %s ea ert%g" % (W, H, view, ert), info)
 
 
 def test_tiny_ea_opaque_ert(R, tiny, tiny_cube):
@@ -171,7 +173,7 @@ def test_ragged_shapes(R, shape, img, mode):
             if mode == "ea":
                 compare_ea(out, ref["image"], TOL_F32, ref["flags"])
             else:
-                compare_mip(out, ref["image"], TOL_F32, ref["flags"])
+                compare_mip(out, ref["image"], TOL_F32, ref["flags"], ref.get("bounds"))
     finally:
         R.release(cube)
 
@@ -195,7 +197,7 @@ def test_maximum_image_extents(R, tiny, tiny_cube, img, mode):
     if mode == "ea":
         compare_ea(got, ref["values"], TOL_F32, ref["flags"])
     else:
-        compare_mip(got, ref["values"], TOL_F32, ref["flags"])
+        compare_mip(got, ref["values"], TOL_F32, ref["flags"], ref.get("bounds"))
 
 
 def test_camera_inside_cube_and_missing_view(R, tiny, tiny_cube):
@@ -275,10 +277,11 @@ def test_stats_count_nominal_samples(R, tiny, tiny_cube):
 # full-size workload in the benchmark's launch configuration, sampled pixels
 # ---------------------------------------------------------------------------
 @pytest.mark.parametrize("mode", ["ea", "mip"])
-def test_full_cube_sampled_pixels(R, full_workload, mode):
+def test_full_cube_whole_frames(R, full_workload, mode):
     """512x512x1024 float32 cube, 1024^2 perspective orbit views, skipping on,
-    early termination at 0.99: the whole image is rendered as in the benchmark
-    and 2000 seeded pixels per view are compared with the reference."""
+    early termination at 0.99, rendered as in the benchmark: two whole frames
+    compared pixel by pixel with the reference, and 2000 seeded pixels of a
+    third view."""
     wl, vol, tf = full_workload
     cube = R.upload(vol, "f32")
     try:
@@ -288,14 +291,20 @@ def test_full_cube_sampled_pixels(R, full_workload, mode):
             set_state(R, wl, tf, cam)
             img, st = R.render(cube, 1024, 1024, mode=mode, stats=True)
             got_img = to_np(img)
-            px = synth.pixel_subset(500 + vi, 1024, 1024, 2000)
-            got = got_img[px[:, 1], px[:, 0]]
-            ref = ref_render(vol, kw, cam, 1024, 1024, mode, "trilinear", pixels=px)
-            if mode == "ea":
-                info = compare_ea(got, ref["values"], TOL_F32, ref["flags"])
+            if vi < 2:
+                ref = ref_render(vol, kw, cam, 1024, 1024, mode, "trilinear")
+                got, want, flags, bnd = got_img, ref["image"], ref["flags"], ref.get("bounds")
+                assert st["samples_nominal"] == int(ref["n_nominal"].sum())
             else:
-                info = compare_mip(got, ref["values"], TOL_F32, ref["flags"])
-            print("full f32 view%d %s %s stats=%s" % (vi, mode, info, st))
+                px = synth.pixel_subset(500 + vi, 1024, 1024, 2000)
+                ref = ref_render(vol, kw, cam, 1024, 1024, mode, "trilinear", pixels=px)
+                got, want, flags, bnd = (got_img[px[:, 1], px[:, 0]], ref["values"], ref["flags"],
+                                         ref.get("bounds"))
+            if mode == "ea":
+                info = compare_ea(got, want, TOL_F32, flags)
+            else:
+                info = compare_mip(got, want, TOL_F32, flags, bnd, clip=wl.clip_k)
+            record("full f32 1024 view%d %s %s" % (vi, mode, "frame" if vi < 2 else "sampled"), info)
             assert st["samples_exec"] <= st["samples_nominal"]
     finally:
         R.release(cube)

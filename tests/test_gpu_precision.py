@@ -20,7 +20,7 @@ import pytest
 
 import oracle
 import synth
-from gpu_common import TOL_16, TOL_F32, compare_ea, compare_mip, ref_render, wl_kwargs
+from gpu_common import TOL_16, TOL_F32, compare_ea, compare_mip, record, ref_render, wl_kwargs
 
 pytestmark = pytest.mark.gpu
 
@@ -62,8 +62,7 @@ def tiny_cube():
 
 
 def report(tag, info):
-    print("%s %s" % (tag, " ".join("%s=%.3g" % (k, v) if isinstance(v, float) else "%s=%s" % (k, v)
-                                   for k, v in info.items())))
+    record(tag, info)
 
 
 @pytest.mark.parametrize("storage", ["f16", "bf16"])
@@ -93,7 +92,7 @@ def test_tiny_gate_and_arithmetic(rend, tiny_cube, storage, mode, view):
         if mode == "ea":
             info = compare_ea(got, ref["image"], TOL_16, ref["flags"], max_ambiguous_frac=0.05)
         else:
-            info = compare_mip(got, ref["image"], TOL_16, ref["flags"])
+            info = compare_mip(got, ref["image"], TOL_16, ref["flags"], ref.get("bounds"))
         report("gate %s %s %s" % (storage, mode, view), info)
         # arithmetic: against the decoded codes
         dec = ref_render(codes_of(vol, storage), kw, cam, W, H, mode, "trilinear",
@@ -101,7 +100,7 @@ def test_tiny_gate_and_arithmetic(rend, tiny_cube, storage, mode, view):
         if mode == "ea":
             info = compare_ea(got, dec["image"], TOL_F32, dec["flags"])
         else:
-            info = compare_mip(got, dec["image"], TOL_F32, dec["flags"])
+            info = compare_mip(got, dec["image"], TOL_F32, dec["flags"], dec.get("bounds"))
         report("arith %s %s %s" % (storage, mode, view), info)
     finally:
         rend.release(cube)
@@ -195,7 +194,8 @@ def test_power_of_two_scaling_bit_identical(rend, tiny_cube, storage):
     assert np.array_equal((outs[0][1] * np.float32(8.0)).view(np.uint32), outs[3][1].view(np.uint32))
 
 
-@pytest.mark.parametrize("storage,size", [("f16", 1024), ("bf16", 1024), ("f16", 2048)])
+@pytest.mark.parametrize("storage,size", [("f16", 1024), ("bf16", 1024), ("f16", 2048),
+                                          ("bf16", 2048)])
 def test_full_cube_sampled_gate(rend, full_workload, storage, size):
     """The full-size cube stored in 16 bits, 1024^2 / 2048^2 perspective views:
     sampled pixels vs the reference on the original float32 values (gate) and
@@ -226,8 +226,8 @@ def test_full_cube_sampled_gate(rend, full_workload, storage, size):
                     g = compare_ea(got, ref["values"], TOL_16, ref["flags"], max_ambiguous_frac=0.05)
                     a = compare_ea(got, dec["values"], TOL_F32, dec["flags"])
                 else:
-                    g = compare_mip(got, ref["values"], TOL_16, ref["flags"])
-                    a = compare_mip(got, dec["values"], TOL_F32, dec["flags"])
+                    g = compare_mip(got, ref["values"], TOL_16, ref["flags"], ref.get("bounds"))
+                    a = compare_mip(got, dec["values"], TOL_F32, dec["flags"], dec.get("bounds"))
                 report("full gate %s %d view%d %s" % (storage, size, vi, mode), g)
                 report("full arith %s %d view%d %s" % (storage, size, vi, mode), a)
     finally:

@@ -136,7 +136,7 @@ def test_served_images_match_renderer_and_reference(env):
         if mode == "ea":
             compare_ea(got, ref["values"], TOL_F32, ref["flags"])
         else:
-            compare_mip(got, ref["values"], TOL_F32, ref["flags"])
+            compare_mip(got, ref["values"], TOL_F32, ref["flags"], ref.get("bounds"))
 
 
 def test_server_state_errors(env):

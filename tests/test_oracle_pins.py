@@ -561,3 +561,130 @@ def test_storage_decode_in_renderer_matches_promoted_values(tiny_cube):
         a = oracle.render(bits, vox_dtype=dt, vox_scale=2.0, **kw)["image"]
         b = oracle.render(dec, **kw)["image"]
         assert np.array_equal(a, b)
+
+
+# ---------------------------------------------------------------------------
+# Ambiguity flags pinned by constructed rays: each flag is raised exactly when
+# the quantity it watches lies within its margin of the decision threshold.
+# ---------------------------------------------------------------------------
+def _flat_tf(kappa):
+    """Two equal rows: extinction kappa and grey colour for every value."""
+    return np.array([[0.5, 0.5, 0.5, kappa], [0.5, 0.5, 0.5, kappa]], dtype=np.float64)
+
+
+@pytest.mark.parametrize("delta,flagged,stop", [(0.5e-5, True, 41), (2e-5, False, 41),
+                                                (-0.5e-5, True, 40), (-2e-5, False, 40)])
+def test_ert_flag_margin(delta, flagged, stop):
+    """Constant cube, rays along z: after k full segments of length 0.5 the
+    opacity is 1 - exp(-0.05 * 0.5 k) (closed form).  The early-termination
+    threshold is put delta away from the opacity after 40 samples: the ERT
+    flag is raised iff |delta| < amb_ert (1e-5), and the ray stops after
+    sample 40 (delta <= 0) or 41 (delta > 0)."""
+    N = (8, 8, 64)
+    vol = np.full(N[::-1], 0.5, dtype=np.float64)
+    a40 = -math.expm1(-0.05 * 0.5 * 40)
+    cam = synth.axis_camera(*N, "z", 4, 4)
+    res = oracle.render(vol, mode=oracle.EA, tf=_flat_tf(0.05), v0=0.0, v1=1.0, camera=cam,
+                        width=4, height=4, step=0.5, ert=a40 + delta, amb_ert=1e-5)
+    fl = res["flags"]
+    assert np.all(fl & oracle.FLAG_ERT_STOPPED)
+    assert np.all(res["n_exec"] == stop)
+    assert np.all(((fl & oracle.FLAG_ERT_AMBIG) > 0) == flagged)
+    assert np.allclose(res["image"][..., 3], -math.expm1(-0.05 * 0.5 * stop), rtol=0, atol=1e-12)
+
+
+@pytest.mark.parametrize("rel,flagged", [(0.5e-4, True), (-0.5e-4, True), (2e-4, False),
+                                         (-2e-4, False)])
+def test_clip_flag_margin(rel, flagged):
+    """A transfer function with a jump at the clip (kappa(clip) > 0): a constant
+    cube whose value lies rel * max(1, |clip|) from the clip is flagged iff
+    |rel| < amb_clip (1e-4).  Below the clip the image is exactly zero; above
+    it, the slab law holds."""
+    N = (6, 6, 10)
+    clip = 3.0
+    v = clip + rel * clip
+    vol = np.full(N[::-1], v, dtype=np.float64)
+    cam = synth.axis_camera(*N, "z", 3, 3)
+    res = oracle.render(vol, mode=oracle.EA, tf=_flat_tf(0.2), v0=0.0, v1=10.0, clip=clip,
+                        camera=cam, width=3, height=3, step=0.5, ert=2.0, amb_clip=1e-4)
+    fl = res["flags"]
+    assert np.all(((fl & oracle.FLAG_CLIP_AMBIG) > 0) == flagged)
+    A = res["image"][..., 3]
+    if rel < 0:
+        assert np.all(res["image"] == 0.0)
+    else:
+        assert np.allclose(A, -math.expm1(-0.2 * 10.0), rtol=0, atol=1e-12)
+
+
+def test_clip_flag_absent_when_transfer_function_is_continuous_at_clip():
+    """With the ramp starting at the clip (kappa(clip) = 0) the result is
+    continuous there: a cube exactly at the clip is not flagged and renders
+    to zero."""
+    N = (6, 6, 10)
+    vol = np.full(N[::-1], 3.0, dtype=np.float64)
+    cam = synth.axis_camera(*N, "z", 3, 3)
+    res = oracle.render(vol, mode=oracle.EA, tf=ramp64(), v0=3.0, v1=20.0, clip=3.0, camera=cam,
+                        width=3, height=3, step=0.5, ert=2.0)
+    assert not np.any(res["flags"] & oracle.FLAG_CLIP_AMBIG)
+    assert np.all(res["image"] == 0.0)
+
+
+@pytest.mark.parametrize("chord,flagged", [(0.5e-6, True), (4e-6, False)])
+def test_graze_flag_margin(chord, flagged):
+    """An orthographic ray along (1, 1, 0)/sqrt(2) that cuts the box's edge at
+    x = N-1/2, y = -1/2: starting on the face y = -1/2 at x = N - 1/2 - a, its
+    chord is a*sqrt(2) (closed form).  The graze flag is raised iff the chord
+    is below amb_graze (1e-6)."""
+    N = (8, 8, 8)
+    a = chord / math.sqrt(2.0)
+    d = np.array([1.0, 1.0, 0.0]) / math.sqrt(2.0)
+    target = np.array([N[0] - 0.5 - a, -0.5, 3.5])
+    cam = synth.Camera(eye=tuple(target - 10.0 * d), target=tuple(target), up=(0, 0, 1),
+                       ortho=True, ortho_w=1.0, ortho_h=1.0)
+    vol = np.full(N[::-1], 1.0, dtype=np.float64)
+    res = oracle.render(vol, mode=oracle.MIP, camera=cam, width=1, height=1, step=0.5,
+                        amb_graze=1e-6)
+    o, dd = oracle.pixel_ray(cam, 1, 1, 0, 0)
+    hit, t0, t1 = oracle.slab(N[::-1], cam, 1, 1, o, dd)
+    assert hit and abs((t1 - t0) - chord) < 1e-12
+    fl = int(res["flags"][0, 0])
+    assert fl & oracle.FLAG_HIT
+    assert bool(fl & oracle.FLAG_GRAZE_AMBIG) == flagged
+
+
+def test_nearest_tie_bounds_are_the_candidate_maxima():
+    """Pixel centres on voxel faces (ties in x): the reference's bounds of the
+    correct maxima equal a brute force over both candidate voxels of every
+    tied coordinate; untied pixels have bounds equal to the value."""
+    N = (4, 4, 4)
+    vol = np.arange(64, dtype=np.float64).reshape(4, 4, 4)
+    cam = synth.Camera(eye=(1.0, 1.5, -10), target=(1.0, 1.5, 1.5), up=(0, -1, 0), ortho=True,
+                       ortho_w=4.0, ortho_h=4.0)
+    res = oracle.render(vol, mode=oracle.MIP, interp=oracle.NEAREST, camera=cam, width=4, height=4)
+    img, b, fl = res["image"], res["bounds"], res["flags"]
+
+    def cands(x, n):
+        s = x + 0.5
+        k = math.floor(s)
+        fr = s - k
+        out = {k}
+        if 0.0 < s < n and (fr < 1e-6 or fr > 1.0 - 1e-6):
+            out.add(k - 1 if fr < 0.5 else k + 1)
+        return sorted(min(max(c, 0), n - 1) for c in out)
+
+    ntie = 0
+    for j in range(4):
+        for i in range(4):
+            o, d = oracle.pixel_ray(cam, 4, 4, i, j)
+            X, Y = cands(o[0], 4), cands(o[1], 4)
+            # samples along z sit at -1/4 + k/2: never a tie; the maximum is at z = 3
+            lo = max(min(vol[z, y, x] for x in X for y in Y) for z in range(4))
+            hi = max(max(vol[z, y, x] for x in X for y in Y) for z in range(4))
+            assert b[j, i, 0] == lo and b[j, i, 1] == hi
+            assert lo <= img[j, i] <= hi
+            tie = bool(fl[j, i] & oracle.FLAG_NEAREST_AMBIG)
+            assert tie == (len(X) > 1 or len(Y) > 1)
+            ntie += tie
+            if not tie:
+                assert lo == hi == img[j, i]
+    assert ntie >= 8
