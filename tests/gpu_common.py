@@ -45,7 +45,8 @@ def compare_ea(gpu, ref, tol, flags=None, max_ambiguous_frac=0.01):
     return info
 
 
-def compare_mip(gpu, ref, tol, flags=None, bounds=None, clip=-math.inf, max_loose_frac=0.01):
+def compare_mip(gpu, ref, tol, flags=None, bounds=None, clip=-math.inf, max_loose_frac=0.01,
+                amb_clip=1e-4):
     """gpu: float32 MIP values; ref: float64 reference values (-inf = miss),
     with the reference's flags and, for nearest sampling, its bounds of the
     correct maxima (..., 2).  Tolerance: tol * max(1, |m|) (MIP values are in
@@ -57,7 +58,8 @@ def compare_mip(gpu, ref, tol, flags=None, bounds=None, clip=-math.inf, max_loos
       * nearest-sampling tie: the value is x (or 0 when x < clip) for some x
         in [lo, hi], the least and greatest maximum over every voxel a tied
         coordinate can round to;
-      * clip floor (maximum within a hair of the clip): 0 or the maximum;
+      * clip floor (maximum within amb_clip * max(1, |clip|) of the clip, the
+        reference's flag margin): 0, or a maximum inside that window;
       * grazing ray (chord within a hair of zero): a miss (-inf), 0, or the
         reference value.
     The last two (loose) kinds are also capped at max_loose_frac of the pixels."""
@@ -94,6 +96,11 @@ def compare_mip(gpu, ref, tol, flags=None, bounds=None, clip=-math.inf, max_loos
         g, r, sc = gpu[loose], ref[loose], scale[loose]
         near = np.isfinite(r) & (np.abs(g - r) <= tol * sc)
         ok = near | (g == 0.0) | (np.isneginf(g) & ((fl[loose] & oracle.FLAG_GRAZE_AMBIG) > 0))
+        if math.isfinite(clip):
+            # the reference floored its maximum to 0 or kept it; the unfloored
+            # maximum lies within the flag's window around the clip
+            win = amb_clip * max(1.0, abs(clip)) + tol * sc
+            ok |= ((fl[loose] & oracle.FLAG_MIPCLIP_AMBIG) > 0) & (np.abs(g - clip) <= win)
         if bounds is not None:
             b = np.asarray(bounds, dtype=np.float64)
             lo, hi = b[..., 0][loose], b[..., 1][loose]

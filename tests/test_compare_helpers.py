@@ -48,6 +48,16 @@ def test_mip_loose_kinds_checked_and_capped():
     bad[0] = 4.0
     with pytest.raises(AssertionError):
         compare_mip(bad, ref, 1e-5, fl)
+    # with a clip of 3: a maximum at the clip within the flag window is correct,
+    # one outside it is not
+    at = ref.copy()
+    at[0] = 0.0
+    gpu_c = at.copy()
+    gpu_c[0] = 3.0 + 0.9e-4 * 3.0
+    compare_mip(gpu_c, at, 1e-5, fl, clip=3.0)
+    gpu_c[0] = 3.0 + 1.2e-4 * 3.0
+    with pytest.raises(AssertionError):
+        compare_mip(gpu_c, at, 1e-5, fl, clip=3.0)
     many = fl.copy()
     many[:10] |= oracle.FLAG_MIPCLIP_AMBIG  # 2.5 % of the pixels
     with pytest.raises(AssertionError):

@@ -173,7 +173,8 @@ def test_ragged_shapes(R, shape, img, mode):
             if mode == "ea":
                 compare_ea(out, ref["image"], TOL_F32, ref["flags"])
             else:
-                compare_mip(out, ref["image"], TOL_F32, ref["flags"], ref.get("bounds"))
+                compare_mip(out, ref["image"], TOL_F32, ref["flags"], ref.get("bounds"),
+                            clip=wl.clip_k * wl.cube.sigma)
     finally:
         R.release(cube)
 
@@ -197,7 +198,8 @@ def test_maximum_image_extents(R, tiny, tiny_cube, img, mode):
     if mode == "ea":
         compare_ea(got, ref["values"], TOL_F32, ref["flags"])
     else:
-        compare_mip(got, ref["values"], TOL_F32, ref["flags"], ref.get("bounds"))
+        compare_mip(got, ref["values"], TOL_F32, ref["flags"], ref.get("bounds"),
+                    clip=wl.clip_k * wl.cube.sigma)
 
 
 def test_camera_inside_cube_and_missing_view(R, tiny, tiny_cube):

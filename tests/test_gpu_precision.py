@@ -92,7 +92,8 @@ def test_tiny_gate_and_arithmetic(rend, tiny_cube, storage, mode, view):
         if mode == "ea":
             info = compare_ea(got, ref["image"], TOL_16, ref["flags"], max_ambiguous_frac=0.05)
         else:
-            info = compare_mip(got, ref["image"], TOL_16, ref["flags"], ref.get("bounds"))
+            info = compare_mip(got, ref["image"], TOL_16, ref["flags"], ref.get("bounds"),
+                               clip=wl.clip_k, amb_clip=TOL_16)
         report("gate %s %s %s" % (storage, mode, view), info)
         # arithmetic: against the decoded codes
         dec = ref_render(codes_of(vol, storage), kw, cam, W, H, mode, "trilinear",
@@ -100,7 +101,8 @@ def test_tiny_gate_and_arithmetic(rend, tiny_cube, storage, mode, view):
         if mode == "ea":
             info = compare_ea(got, dec["image"], TOL_F32, dec["flags"])
         else:
-            info = compare_mip(got, dec["image"], TOL_F32, dec["flags"], dec.get("bounds"))
+            info = compare_mip(got, dec["image"], TOL_F32, dec["flags"], dec.get("bounds"),
+                               clip=wl.clip_k)
         report("arith %s %s %s" % (storage, mode, view), info)
     finally:
         rend.release(cube)
@@ -226,8 +228,10 @@ def test_full_cube_sampled_gate(rend, full_workload, storage, size):
                     g = compare_ea(got, ref["values"], TOL_16, ref["flags"], max_ambiguous_frac=0.05)
                     a = compare_ea(got, dec["values"], TOL_F32, dec["flags"])
                 else:
-                    g = compare_mip(got, ref["values"], TOL_16, ref["flags"], ref.get("bounds"))
-                    a = compare_mip(got, dec["values"], TOL_F32, dec["flags"], dec.get("bounds"))
+                    g = compare_mip(got, ref["values"], TOL_16, ref["flags"], ref.get("bounds"),
+                                    clip=wl.clip_k, amb_clip=TOL_16)
+                    a = compare_mip(got, dec["values"], TOL_F32, dec["flags"], dec.get("bounds"),
+                                    clip=wl.clip_k)
                 report("full gate %s %d view%d %s" % (storage, size, vi, mode), g)
                 report("full arith %s %d view%d %s" % (storage, size, vi, mode), a)
     finally:

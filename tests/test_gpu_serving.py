@@ -136,7 +136,8 @@ def test_served_images_match_renderer_and_reference(env):
         if mode == "ea":
             compare_ea(got, ref["values"], TOL_F32, ref["flags"])
         else:
-            compare_mip(got, ref["values"], TOL_F32, ref["flags"], ref.get("bounds"))
+            compare_mip(got, ref["values"], TOL_F32, ref["flags"], ref.get("bounds"),
+                        clip=wl.clip_k)
 
 
 def test_server_state_errors(env):
