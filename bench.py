@@ -39,13 +39,12 @@ def log(*a):
 
 
 def cpu_threads():
-    """Host threads for CPU work: the cores this process may run on, capped at
-    16, the host CPU share that comes with one GPU on the benchmark machines."""
+    """Host threads for CPU work: every core this process may run on."""
     try:
         n = len(os.sched_getaffinity(0))
     except AttributeError:
         n = os.cpu_count() or 1
-    return max(1, min(n, 16))
+    return max(1, n)
 
 
 def cpu_model():

@@ -140,8 +140,10 @@ typedef struct {
     uint64_t aux_bytes;         /* device bytes of tables and statistics */
     float vmin, vmax;           /* range of stored values times sigma_scale */
     int32_t x_chunks;           /* 16-byte chunks of x per slot row (9 float32, 5 16-bit) */
-    int32_t reserved;
-    /* device pointers, for inspection: */
+    uint8_t resident;           /* 1 if the bricks are in device memory now */
+    uint8_t registered;         /* 1 if registered with a host source (vr_cube_register) */
+    uint16_t reserved;
+    /* device pointers, NULL while a registered cube is not resident: */
     const void* pool;           /* brick slots; slot of brick (bx,by,bz) is
                                    (bz*bricks_y + by)*bricks_x + bx.  A slot holds local voxels
                                    lx < 16*x_chunks/elem, ly < 36, lz < 34, each the
@@ -158,9 +160,12 @@ typedef struct {
 /* --- context ------------------------------------------------------------ */
 
 /* Create a context on HIP device `device`.  hbm_budget_bytes caps the device
- * memory the context's cubes may hold (0 = no cap).  device = -1 creates a
- * host-only context that validates arguments and keeps state but rejects
- * device work with VR_EDEVICE.  alloc may be NULL. */
+ * memory the context's cubes may hold, their brick pools and per-cell
+ * statistics (0 = no cap; skip masks, about 0.01 % of a pool, and scratch are
+ * not counted).  Uploaded cubes count until released; registered cubes
+ * (vr_cube_register) are admitted and evicted within the cap.  device = -1
+ * creates a host-only context that validates arguments and keeps state but
+ * rejects device work with VR_EDEVICE.  alloc may be NULL. */
 vr_status vr_create(int32_t device, uint64_t hbm_budget_bytes, const vr_allocator* alloc,
                     vr_ctx* out);
 
@@ -188,8 +193,69 @@ vr_status vr_cube_upload(vr_ctx ctx, const void* src, int32_t src_dtype, int32_t
                          int64_t nx, int64_t ny, int64_t nz, int32_t storage, double sigma_scale,
                          void* hip_stream, vr_cube* out);
 
+/* Register a cube whose voxels stay in caller-owned host memory: src, nx, ny,
+ * nz, src_dtype, storage and sigma_scale as for vr_cube_upload from host
+ * memory.  Nothing is uploaded yet.  Whenever a render, batch or served
+ * request needs the cube and it is not resident, the library admits it:
+ * within the context's memory budget it evicts idle registered cubes, least
+ * recently used first (their host copies stay with the caller), and uploads
+ * this one.  A served request whose cube cannot be admitted while other
+ * requests hold device memory waits in the queue until memory frees up; the
+ * scheduler lets requests for resident cubes pass it for a few launches and
+ * then drains the device for it, so no request starves.  This is the one-GPU
+ * form of the paper's scheduling of sub-cubes of data larger than a single
+ * GPU's memory onto the available GPUs (Sec. 2; Sec. 3.1, process steps 1-2).
+ * The caller keeps src unchanged and valid until vr_cube_release.  Errors:
+ * VR_EINVAL / VR_EUNSUPPORTED as for vr_cube_upload; VR_ENOMEM if the cube
+ * alone needs more device memory than the whole budget. */
+vr_status vr_cube_register(vr_ctx ctx, const void* src, int32_t src_dtype, int64_t nx, int64_t ny,
+                           int64_t nz, int32_t storage, double sigma_scale, vr_cube* out);
+
+/* --- noise-aware form --------------------------------------------------------
+ * The noise of a spectral cube varies with frequency, and the paper gives
+ * special attention to data of low signal-to-noise ratio (abstract; Sec. 2).
+ * These calls estimate each channel's noise and store the cube in units of
+ * it, so that the clip k of vr_set_noise_clip(k, 1) removes everything below
+ * k*sigma(nu) channel by channel, and transfer functions are given in S/N. */
+
+/* Robust noise level of every frequency channel (z plane) of an nx*ny*nz
+ * float32 cube (x fastest) in host (src_on_device = 0) or device memory:
+ * median = the lower median of the channel's nx*ny values (order statistic
+ * floor((n-1)/2)), mad = the lower median of |v - median| (float32
+ * deviations), sigma = 1.4826 * mad.  Computed on the device (exact order
+ * statistics); each output is a host array of nz floats, any may be NULL.
+ * Values must be finite.  Returns once the outputs are written.  Errors:
+ * VR_EINVAL (NULL src, nx*ny >= 2^31, nz > 65536), VR_EDEVICE. */
+vr_status vr_estimate_channel_noise(vr_ctx ctx, const float* src, int32_t src_on_device, int64_t nx,
+                                    int64_t ny, int64_t nz, void* hip_stream, float* median_out,
+                                    float* mad_out, float* sigma_out);
+
+/* Upload a float32 cube as vr_cube_upload does, storing value / divisor[z]
+ * (round to nearest even for 16-bit storage) with one positive divisor per
+ * channel (host array of nz floats, e.g. the sigma of
+ * vr_estimate_channel_noise).  The cube's data units are then units of each
+ * channel's divisor: transfer-function domains, clips and MIP outputs are in
+ * those units (sigma_scale is 1).  Errors as for vr_cube_upload; VR_EINVAL
+ * for a divisor that is not positive and finite. */
+vr_status vr_cube_upload_scaled(vr_ctx ctx, const float* src, int32_t src_on_device, int64_t nx,
+                                int64_t ny, int64_t nz, int32_t storage, const float* channel_divisor,
+                                void* hip_stream, vr_cube* out);
+
 /* Release a cube.  VR_EBUSY if queued serving requests still reference it. */
 vr_status vr_cube_release(vr_ctx ctx, vr_cube cube);
+
+typedef struct {
+    uint64_t budget_bytes;      /* the context's cap (0: none) */
+    uint64_t used_bytes;        /* device bytes counted against the budget */
+    uint64_t cubes;             /* live cube handles */
+    uint64_t resident_cubes;    /* of which resident in device memory */
+    uint64_t registered_cubes;  /* of which registered with a host source */
+    uint64_t uploads;           /* on-demand admissions of registered cubes so far */
+    uint64_t evictions;         /* registered cubes evicted to make room so far */
+} vr_memory_stats;
+
+/* Memory accounting of a context (admission and eviction counters). */
+vr_status vr_get_memory_stats(vr_ctx ctx, vr_memory_stats* out);
 
 /* Describe a cube (sizes, layout, device pointers for inspection). */
 vr_status vr_cube_get_info(vr_ctx ctx, vr_cube cube, vr_cube_info* out);

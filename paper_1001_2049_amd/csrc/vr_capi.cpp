@@ -57,6 +57,15 @@ vr_status Uses::sync() const {
     return VR_OK;
 }
 
+bool Uses::done() const {
+    for (const auto& e : ev) {
+        const hipError_t q = hipEventQuery(e.second);
+        if (q == hipErrorNotReady) return false;
+        if (q != hipSuccess) (void)hipGetLastError();  // reported by the next synchronising call
+    }
+    return true;
+}
+
 void Uses::destroy() {
     for (auto& e : ev) (void)hipEventDestroy(e.second);
     ev.clear();
@@ -68,9 +77,14 @@ uint64_t Cube::bytes() const {
     return b;
 }
 
+static uint64_t alloc_size(uint64_t bytes) { return ((bytes ? bytes : 256) + 255) & ~uint64_t(255); }
+
+uint64_t Cube::need_bytes() const {
+    return alloc_size((uint64_t)nslots * stride) + alloc_size((uint64_t)nslots * 2 * VR_CELLS_PER_BRICK * 4);
+}
+
 vr_status dev_alloc(Ctx* c, DevBuf& b, uint64_t bytes, bool budgeted) {
-    if (bytes == 0) bytes = 256;
-    bytes = (bytes + 255) & ~uint64_t(255);
+    bytes = alloc_size(bytes);
     if (budgeted && c->budget && c->used + bytes > c->budget) {
         set_error("device memory budget exceeded (" + std::to_string(c->used + bytes) + " > " +
                   std::to_string(c->budget) + " bytes)");
@@ -290,12 +304,13 @@ static vr_status get_mask(Ctx* c, Cube* cube, int mode, Tf* tf, float clip_s, hi
     if (cube->masks.size() < 8 || !lru) {
         cube->masks.emplace_back();
         e = &cube->masks.back();
-        vr_status st = dev_alloc(c, e->buf, (uint64_t)cube->nslots * 8, true);
+        // skip masks (about 0.01 % of a pool) are not counted against the budget
+        vr_status st = dev_alloc(c, e->buf, (uint64_t)cube->nslots * 8, false);
         if (st == VR_OK)
             st = dev_alloc(c, e->bits, (uint64_t)vr_cellbits_words(cube->Bx, cube->By, cube->Bz) * 4,
-                           true);
+                           false);
         if (st != VR_OK) {
-            dev_free(c, e->buf, true);
+            dev_free(c, e->buf, false);
             cube->masks.pop_back();
             return st;
         }
@@ -317,10 +332,14 @@ static vr_status get_mask(Ctx* c, Cube* cube, int mode, Tf* tf, float clip_s, hi
         n = tf->n;
         kpos = (const int*)tf->dev_kpos.ptr;
     }
+    if (mode == VR_MIP && !e->cellmax.ptr) {
+        vr_status st = dev_alloc(c, e->cellmax, (uint64_t)cube->nslots * VR_CELLS_PER_BRICK * 4, false);
+        if (st != VR_OK) return st;
+    }
     vr_status st = hip_check(
         vr_launch_classify((const float*)cube->cellmm.ptr, (uint64_t*)e->buf.ptr,
-                           (uint32_t*)e->bits.ptr, cube->Bx, cube->By, cube->Bz, mode, clip_s, scale,
-                           bias, n, kpos, s),
+                           (uint32_t*)e->bits.ptr, (float*)e->cellmax.ptr, cube->Bx, cube->By,
+                           cube->Bz, mode, clip_s, scale, bias, n, kpos, s),
         "classify launch");
     if (st == VR_OK) st = hip_check(hipEventRecord(e->ready, s), "hipEventRecord");
     if (st != VR_OK) return st;
@@ -384,6 +403,7 @@ vr_status build_request(Ctx* c, Cube* cube, Tf* tf, float clip, const vr_camera&
         if (st != VR_OK) return st;
         R.cube.mask = (const uint64_t*)me->buf.ptr;
         R.cube.cellbits = (const uint32_t*)me->bits.ptr;
+        R.cube.cellmax = p.mode == VR_MIP ? (const float*)me->cellmax.ptr : nullptr;
         if (mask_used) *mask_used = me;
     }
     return VR_OK;
@@ -570,7 +590,8 @@ static vr_status enqueue_batch(Ctx* c, BatchBufs& bb, int count, int nitems, siz
                                DevCounters* dev_counters, hipStream_t s, bool use_graph) {
     const size_t rq_bytes = (size_t)(use_graph ? bb.reqs_cap : count) * sizeof(DevReq);
     const size_t it_bytes = (size_t)(use_graph ? bb.items_cap : nitems) * sizeof(DevItem);
-    const int grid = use_graph ? c->num_cu : std::max(1, std::min(nitems, c->num_cu));
+    const int slots = c->num_cu * VR_WG_PER_CU;  // resident workgroups
+    const int grid = use_graph ? slots : std::max(1, std::min(nitems, slots));
     g_stage = "batch enqueue";
     auto record = [&]() -> vr_status {
         vr_status st = hip_check(hipMemcpyAsync(bb.hdr.ptr, bb.pin_hdr, 16, hipMemcpyHostToDevice, s),
@@ -622,6 +643,18 @@ vr_status launch_requests(Ctx* c, BatchBufs& bb, const vr_request* reqs, int cou
     if (st != VR_OK) return st;
     int max_tf_n = 0, k = 0;
     std::vector<MaskEntry*> used((size_t)count, nullptr);
+    g_stage = "cube admission";
+    std::vector<Cube*> cubes_in;  // cubes of this launch: none may evict another
+    for (int r = 0; r < count; ++r) {
+        Cube* cube = find_cube(c, reqs[r].cube);
+        st = ensure_resident(c, cube, s, true, cubes_in);
+        if (st == VR_EBUSY) {
+            set_error("the cubes of this batch do not fit the memory budget together");
+            st = VR_ENOMEM;
+        }
+        if (st != VR_OK) return st;
+        if (std::find(cubes_in.begin(), cubes_in.end(), cube) == cubes_in.end()) cubes_in.push_back(cube);
+    }
     g_stage = "request set-up";
     c->launch_stamp = c->mask_stamp;
     for (int r = 0; r < count; ++r) {
@@ -642,7 +675,7 @@ vr_status launch_requests(Ctx* c, BatchBufs& bb, const vr_request* reqs, int cou
     for (int r = 0; r < count; ++r) bb.pin_reqs[r].box_bytes = vr_box_bytes(max_tf_n);
     bb.pin_hdr[0] = nitems;
     if (nitems > 0) {
-        const size_t lds = (size_t)max_tf_n * 32 + 2 * (size_t)vr_box_bytes(max_tf_n);
+        const size_t lds = (size_t)vr_lds_reserve(max_tf_n) + 2 * (size_t)vr_box_bytes(max_tf_n);
         st = enqueue_batch(c, bb, count, nitems, lds, dev_counters, s, use_graph);
         if (st != VR_OK) return st;
     }
@@ -710,21 +743,179 @@ static vr_status release_tf(Ctx* c, Tf* t) {
     return VR_OK;
 }
 
-static vr_status release_cube(Ctx* c, Cube* cube) {
+// Free a cube's device memory (pool, statistics, skip masks) once every
+// queued use of it has completed.
+static vr_status drop_device(Ctx* c, Cube* cube) {
     vr_status st = cube->uses.sync();
     for (auto& m : cube->masks)
         if (st == VR_OK) st = m.uses.sync();
     if (st != VR_OK) return st;
     cube->uses.destroy();
     for (auto& m : cube->masks) {
-        dev_free(c, m.buf, true);
-        dev_free(c, m.bits, true);
+        dev_free(c, m.buf, false);
+        dev_free(c, m.bits, false);
+        dev_free(c, m.cellmax, false);
         m.uses.destroy();
         if (m.ready) (void)hipEventDestroy(m.ready);
     }
+    cube->masks.clear();
     dev_free(c, cube->pool, true);
     dev_free(c, cube->cellmm, true);
+    cube->resident = false;
+    return VR_OK;
+}
+
+static vr_status release_cube(Ctx* c, Cube* cube) {
+    vr_status st = drop_device(c, cube);
+    if (st != VR_OK) return st;
     c->cubes.erase(cube->id);
+    return VR_OK;
+}
+
+// Brick geometry of an nx*ny*nz cube stored as `storage`.
+static vr_status cube_geometry(Cube* cube, int64_t nx, int64_t ny, int64_t nz, int storage,
+                               double sigma) {
+    cube->nx = nx;
+    cube->ny = ny;
+    cube->nz = nz;
+    cube->storage = storage;
+    cube->sigma = sigma;
+    cube->Bx = (int)((nx + VR_BRICK - 1) / VR_BRICK);
+    cube->By = (int)((ny + VR_BRICK - 1) / VR_BRICK);
+    cube->Bz = (int)((nz + VR_BRICK - 1) / VR_BRICK);
+    const int64_t ns = (int64_t)cube->Bx * cube->By * cube->Bz;
+    if (ns > (int64_t)1 << 30) {
+        set_error("cube too large");
+        return VR_EINVAL;
+    }
+    cube->nslots = (int)ns;
+    cube->xch = VR_XCH(storage);
+    cube->stride = ((uint64_t)VR_SLOT_ZP * VR_SLOT_YG * cube->xch * 128 + 255) & ~uint64_t(255);
+    return VR_OK;
+}
+
+// Allocate a cube's pool and statistics and build its bricks from src (host or
+// device memory); returns once src may be reused.  On failure nothing stays
+// allocated.
+static vr_status cube_fill(Ctx* c, Cube* cube, const void* src, int src_dtype, int src_on_device,
+                           hipStream_t s, const float* zdiv_host = nullptr) {
+    auto cleanup = [&]() {
+        dev_free(c, cube->pool, true);
+        dev_free(c, cube->cellmm, true);
+    };
+    const int64_t nx = cube->nx, ny = cube->ny, nz = cube->nz;
+    vr_status st = dev_alloc(c, cube->pool, (uint64_t)cube->nslots * cube->stride, true);
+    if (st == VR_OK)
+        st = dev_alloc(c, cube->cellmm, (uint64_t)cube->nslots * 2 * VR_CELLS_PER_BRICK * 4, true);
+    if (st != VR_OK) {
+        cleanup();
+        return st;
+    }
+    const int src_kind = src_dtype == VR_F32 ? 0 : src_dtype;
+    const uint64_t selem = src_dtype == VR_F32 ? 4 : 2;
+    const uint64_t plane = (uint64_t)nx * ny * selem;
+    DevBuf stage, zdiv;
+    if (zdiv_host) {
+        st = dev_alloc(c, zdiv, (uint64_t)nz * 4, false);
+        if (st == VR_OK)
+            st = hip_check(hipMemcpyAsync(zdiv.ptr, zdiv_host, (size_t)nz * 4, hipMemcpyHostToDevice, s),
+                           "hipMemcpyAsync");
+        if (st != VR_OK) {
+            (void)hipStreamSynchronize(s);
+            dev_free(c, zdiv, false);
+            cleanup();
+            return st;
+        }
+    }
+    if (!src_on_device) {
+        // a brick layer reads planes z0 .. z0 + 33 (apron and padding, edge-clamped)
+        st = dev_alloc(c, stage, plane * (uint64_t)std::min<int64_t>(nz, 2 * VR_SLOT_ZP), false);
+        if (st != VR_OK) {
+            (void)hipStreamSynchronize(s);
+            dev_free(c, zdiv, false);
+            cleanup();
+            return st;
+        }
+    }
+    for (int bz = 0; bz < cube->Bz && st == VR_OK; ++bz) {
+        const int64_t z0 = (int64_t)bz * VR_BRICK;
+        const int64_t z1 = std::min<int64_t>(z0 + 2 * VR_SLOT_ZP, nz);
+        const void* slab = src;
+        int64_t z_first = 0;
+        if (!src_on_device) {
+            st = hip_check(hipMemcpyAsync(stage.ptr, (const uint8_t*)src + (uint64_t)z0 * plane,
+                                          (size_t)((z1 - z0) * plane), hipMemcpyHostToDevice, s),
+                           "hipMemcpyAsync");
+            if (st != VR_OK) break;
+            slab = stage.ptr;
+            z_first = z0;
+        }
+        st = hip_check(vr_launch_brick_build(src_kind, cube->storage, slab, nx, ny, nz, z_first, bz,
+                                             cube->Bx, cube->By, (uint8_t*)cube->pool.ptr,
+                                             cube->stride, cube->xch, (float*)cube->cellmm.ptr,
+                                             (float)cube->sigma, (const float*)zdiv.ptr, s),
+                       "brick build launch");
+    }
+    vr_status st2 = hip_check(hipStreamSynchronize(s), "hipStreamSynchronize");
+    if (stage.ptr) dev_free(c, stage, false);
+    if (zdiv.ptr) dev_free(c, zdiv, false);
+    if (st == VR_OK) st = st2;
+    if (st != VR_OK) {
+        cleanup();
+        return st;
+    }
+    cube->resident = true;
+    cube->lru = ++c->lru_clock;
+    return VR_OK;
+}
+
+// Evict idle registered cubes (least recently used first; never `self` or a
+// cube in `keep`) until `need` more bytes fit the budget.
+static vr_status make_room(Ctx* c, uint64_t need, const Cube* self, bool may_wait,
+                           const std::vector<Cube*>& keep) {
+    while (c->budget && c->used + need > c->budget) {
+        Cube* victim = nullptr;
+        bool waiting = false;  // some candidate is idle but for work in flight
+        for (auto& kv : c->cubes) {
+            Cube* o = kv.second.get();
+            if (o == self || !o->resident || !o->host_src || o->pins > 0) continue;
+            if (std::find(keep.begin(), keep.end(), o) != keep.end()) continue;
+            if (!may_wait && !o->uses.done()) {
+                waiting = true;
+                continue;
+            }
+            if (!victim || o->lru < victim->lru) victim = o;
+        }
+        if (!victim) {
+            if (waiting || !keep.empty()) {
+                set_error("cube does not fit the memory budget while other work holds it");
+                return VR_EBUSY;
+            }
+            bool pinned = false;
+            for (auto& kv : c->cubes) pinned = pinned || (kv.second->resident && kv.second->pins > 0);
+            set_error("cube of " + std::to_string(need) + " bytes does not fit the memory budget (" +
+                      std::to_string(c->used) + " of " + std::to_string(c->budget) +
+                      " bytes held by cubes that cannot be evicted now)");
+            return pinned ? VR_EBUSY : VR_ENOMEM;
+        }
+        vr_status st = drop_device(c, victim);
+        if (st != VR_OK) return st;
+        ++c->evictions;
+    }
+    return VR_OK;
+}
+
+vr_status ensure_resident(Ctx* c, Cube* cube, hipStream_t s, bool may_wait,
+                          const std::vector<Cube*>& keep) {
+    if (cube->resident) {
+        cube->lru = ++c->lru_clock;
+        return VR_OK;
+    }
+    vr_status st = make_room(c, cube->need_bytes(), cube, may_wait, keep);
+    if (st != VR_OK) return st;
+    st = cube_fill(c, cube, cube->host_src, cube->src_dtype, 0, s);
+    if (st != VR_OK) return st;
+    ++c->uploads;
     return VR_OK;
 }
 
@@ -869,71 +1060,200 @@ vr_status vr_cube_upload(vr_ctx ctx, const void* src, int32_t src_dtype, int32_t
         if (st != VR_OK) return st;
         hipStream_t s = (hipStream_t)hip_stream;
         std::unique_ptr<Cube> cube(new Cube());
-        cube->nx = nx;
-        cube->ny = ny;
-        cube->nz = nz;
-        cube->storage = storage;
-        cube->sigma = sigma_scale;
-        cube->Bx = (int)((nx + VR_BRICK - 1) / VR_BRICK);
-        cube->By = (int)((ny + VR_BRICK - 1) / VR_BRICK);
-        cube->Bz = (int)((nz + VR_BRICK - 1) / VR_BRICK);
-        const int64_t ns = (int64_t)cube->Bx * cube->By * cube->Bz;
-        if (ns > (int64_t)1 << 30) {
-            set_error("cube too large");
+        st = cube_geometry(cube.get(), nx, ny, nz, storage, sigma_scale);
+        if (st != VR_OK) return st;
+        // idle registered cubes give way to an uploaded one
+        st = make_room(c, cube->need_bytes(), nullptr, true, {});
+        if (st == VR_EBUSY) st = VR_ENOMEM;
+        if (st != VR_OK) return st;
+        st = cube_fill(c, cube.get(), src, src_dtype, src_on_device, s);
+        if (st != VR_OK) return st;
+        cube->id = c->next_cube++;
+        *out = cube->id;
+        c->cubes[cube->id] = std::move(cube);
+        return VR_OK;
+    });
+}
+
+vr_status vr_cube_register(vr_ctx ctx, const void* src, int32_t src_dtype, int64_t nx, int64_t ny,
+                           int64_t nz, int32_t storage, double sigma_scale, vr_cube* out) {
+    if (!ctx || !out || !src) {
+        set_error("ctx, src and out must be non-NULL");
+        return VR_EINVAL;
+    }
+    *out = 0;
+    if (nx < 2 || ny < 2 || nz < 2 || nx > 65536 || ny > 65536 || nz > 65536) {
+        set_error("cube dimensions must lie in [2, 65536]");
+        return VR_EINVAL;
+    }
+    if (storage != VR_F32 && storage != VR_F16 && storage != VR_BF16) {
+        set_error("storage must be VR_F32, VR_F16 or VR_BF16");
+        return VR_EINVAL;
+    }
+    if (src_dtype != VR_F32 && src_dtype != VR_F16 && src_dtype != VR_BF16) {
+        set_error("src_dtype must be VR_F32, VR_F16 or VR_BF16");
+        return VR_EINVAL;
+    }
+    if (src_dtype != VR_F32 && src_dtype != storage) {
+        set_error("16-bit sources are stored as-is: storage must equal src_dtype");
+        return VR_EUNSUPPORTED;
+    }
+    if (!(sigma_scale > 0.0) || !std::isfinite(sigma_scale)) {
+        set_error("sigma_scale must be positive and finite");
+        return VR_EINVAL;
+    }
+    Ctx* c = (Ctx*)ctx;
+    VR_GUARD({
+        std::lock_guard<std::recursive_mutex> lk(c->mu);
+        if (c->host_only()) {
+            set_error("host-only context cannot hold cubes");
+            return VR_EDEVICE;
+        }
+        std::unique_ptr<Cube> cube(new Cube());
+        vr_status st = cube_geometry(cube.get(), nx, ny, nz, storage, sigma_scale);
+        if (st != VR_OK) return st;
+        if (c->budget && cube->need_bytes() > c->budget) {
+            set_error("cube needs " + std::to_string(cube->need_bytes()) +
+                      " device bytes, more than the whole budget of " + std::to_string(c->budget));
+            return VR_ENOMEM;
+        }
+        cube->host_src = src;
+        cube->src_dtype = src_dtype;
+        cube->id = c->next_cube++;
+        *out = cube->id;
+        c->cubes[cube->id] = std::move(cube);
+        return VR_OK;
+    });
+}
+
+vr_status vr_get_memory_stats(vr_ctx ctx, vr_memory_stats* out) {
+    if (!ctx || !out) {
+        set_error("ctx and out must be non-NULL");
+        return VR_EINVAL;
+    }
+    Ctx* c = (Ctx*)ctx;
+    VR_GUARD({
+        std::lock_guard<std::recursive_mutex> lk(c->mu);
+        std::memset(out, 0, sizeof(*out));
+        out->budget_bytes = c->budget;
+        out->used_bytes = c->used;
+        for (auto& kv : c->cubes) {
+            out->cubes += 1;
+            out->resident_cubes += kv.second->resident ? 1 : 0;
+            out->registered_cubes += kv.second->host_src ? 1 : 0;
+        }
+        out->uploads = c->uploads;
+        out->evictions = c->evictions;
+        return VR_OK;
+    });
+}
+
+vr_status vr_estimate_channel_noise(vr_ctx ctx, const float* src, int32_t src_on_device, int64_t nx,
+                                    int64_t ny, int64_t nz, void* hip_stream, float* median_out,
+                                    float* mad_out, float* sigma_out) {
+    if (!ctx || !src) {
+        set_error("ctx and src must be non-NULL");
+        return VR_EINVAL;
+    }
+    if (nx < 1 || ny < 1 || nz < 1 || nx * ny >= ((int64_t)1 << 31) || nz > 65536) {
+        set_error("channel size nx*ny must lie in [1, 2^31) and nz in [1, 65536]");
+        return VR_EINVAL;
+    }
+    if (src_on_device != 0 && src_on_device != 1) {
+        set_error("src_on_device must be 0 or 1");
+        return VR_EINVAL;
+    }
+    Ctx* c = (Ctx*)ctx;
+    VR_GUARD({
+        std::lock_guard<std::recursive_mutex> lk(c->mu);
+        if (c->host_only()) {
+            set_error("host-only context cannot estimate on the device");
+            return VR_EDEVICE;
+        }
+        vr_status st = hip_check(hipSetDevice(c->device), "hipSetDevice");
+        if (st != VR_OK) return st;
+        hipStream_t s = (hipStream_t)hip_stream;
+        const uint64_t plane = (uint64_t)nx * ny;
+        DevBuf out, stage;
+        st = dev_alloc(c, out, (uint64_t)nz * 12, false);
+        // host sources are staged a group of channels at a time (<= 256 MiB)
+        const int64_t group = src_on_device ? nz
+                                            : std::max<int64_t>(1, std::min<int64_t>(nz, ((int64_t)256 << 20) / (int64_t)(plane * 4)));
+        if (st == VR_OK && !src_on_device) st = dev_alloc(c, stage, plane * 4 * (uint64_t)group, false);
+        float* med = (float*)out.ptr;
+        for (int64_t z0 = 0; z0 < nz && st == VR_OK; z0 += group) {
+            const int64_t np = std::min<int64_t>(group, nz - z0);
+            const float* p = src + (uint64_t)z0 * plane;
+            if (!src_on_device) {
+                st = hip_check(hipMemcpyAsync(stage.ptr, p, (size_t)(np * plane * 4), hipMemcpyHostToDevice, s),
+                               "hipMemcpyAsync");
+                p = (const float*)stage.ptr;
+            }
+            if (st == VR_OK)
+                st = hip_check(vr_launch_channel_noise(p, (int64_t)plane, z0, (int)np, med, med + nz,
+                                                       med + 2 * nz, s),
+                               "noise launch");
+        }
+        std::vector<float> h((size_t)nz * 3);
+        if (st == VR_OK)
+            st = hip_check(hipMemcpyAsync(h.data(), out.ptr, h.size() * 4, hipMemcpyDeviceToHost, s),
+                           "hipMemcpyAsync");
+        vr_status st2 = hip_check(hipStreamSynchronize(s), "hipStreamSynchronize");
+        dev_free(c, out, false);
+        dev_free(c, stage, false);
+        if (st == VR_OK) st = st2;
+        if (st != VR_OK) return st;
+        if (median_out) std::memcpy(median_out, h.data(), (size_t)nz * 4);
+        if (mad_out) std::memcpy(mad_out, h.data() + nz, (size_t)nz * 4);
+        if (sigma_out) std::memcpy(sigma_out, h.data() + 2 * nz, (size_t)nz * 4);
+        return VR_OK;
+    });
+}
+
+vr_status vr_cube_upload_scaled(vr_ctx ctx, const float* src, int32_t src_on_device, int64_t nx,
+                                int64_t ny, int64_t nz, int32_t storage, const float* channel_divisor,
+                                void* hip_stream, vr_cube* out) {
+    if (!ctx || !out || !src || !channel_divisor) {
+        set_error("ctx, src, channel_divisor and out must be non-NULL");
+        return VR_EINVAL;
+    }
+    *out = 0;
+    if (nx < 2 || ny < 2 || nz < 2 || nx > 65536 || ny > 65536 || nz > 65536) {
+        set_error("cube dimensions must lie in [2, 65536]");
+        return VR_EINVAL;
+    }
+    if (storage != VR_F32 && storage != VR_F16 && storage != VR_BF16) {
+        set_error("storage must be VR_F32, VR_F16 or VR_BF16");
+        return VR_EINVAL;
+    }
+    if (src_on_device != 0 && src_on_device != 1) {
+        set_error("src_on_device must be 0 or 1");
+        return VR_EINVAL;
+    }
+    for (int64_t z = 0; z < nz; ++z) {
+        if (!(channel_divisor[z] > 0.0f) || !std::isfinite(channel_divisor[z])) {
+            set_error("channel divisor " + std::to_string(z) + " is not positive and finite");
             return VR_EINVAL;
         }
-        cube->nslots = (int)ns;
-        cube->xch = VR_XCH(storage);
-        cube->stride = ((uint64_t)VR_SLOT_ZP * VR_SLOT_YG * cube->xch * 128 + 255) & ~uint64_t(255);
-        auto cleanup = [&]() {
-            dev_free(c, cube->pool, true);
-            dev_free(c, cube->cellmm, true);
-        };
-        st = dev_alloc(c, cube->pool, (uint64_t)ns * cube->stride, true);
-        if (st == VR_OK)
-            st = dev_alloc(c, cube->cellmm, (uint64_t)ns * 2 * VR_CELLS_PER_BRICK * 4, true);
-        if (st != VR_OK) {
-            cleanup();
-            return st;
+    }
+    Ctx* c = (Ctx*)ctx;
+    VR_GUARD({
+        std::lock_guard<std::recursive_mutex> lk(c->mu);
+        if (c->host_only()) {
+            set_error("host-only context cannot hold cubes");
+            return VR_EDEVICE;
         }
-        const int src_kind = src_dtype == VR_F32 ? 0 : src_dtype;
-        const uint64_t selem = src_dtype == VR_F32 ? 4 : 2;
-        const uint64_t plane = (uint64_t)nx * ny * selem;
-        DevBuf stage;
-        if (!src_on_device) {
-            // a brick layer reads planes z0 .. z0 + 33 (apron and padding, edge-clamped)
-            st = dev_alloc(c, stage, plane * (uint64_t)std::min<int64_t>(nz, 2 * VR_SLOT_ZP), false);
-            if (st != VR_OK) {
-                cleanup();
-                return st;
-            }
-        }
-        for (int bz = 0; bz < cube->Bz && st == VR_OK; ++bz) {
-            const int64_t z0 = (int64_t)bz * VR_BRICK;
-            const int64_t z1 = std::min<int64_t>(z0 + 2 * VR_SLOT_ZP, nz);
-            const void* slab = src;
-            int64_t z_first = 0;
-            if (!src_on_device) {
-                st = hip_check(hipMemcpyAsync(stage.ptr, (const uint8_t*)src + (uint64_t)z0 * plane,
-                                              (size_t)((z1 - z0) * plane), hipMemcpyHostToDevice, s),
-                               "hipMemcpyAsync");
-                if (st != VR_OK) break;
-                slab = stage.ptr;
-                z_first = z0;
-            }
-            st = hip_check(vr_launch_brick_build(src_kind, storage, slab, nx, ny, nz, z_first, bz,
-                                                 cube->Bx, cube->By, (uint8_t*)cube->pool.ptr,
-                                                 cube->stride, cube->xch, (float*)cube->cellmm.ptr,
-                                                 (float)sigma_scale, s),
-                           "brick build launch");
-        }
-        vr_status st2 = hip_check(hipStreamSynchronize(s), "hipStreamSynchronize");
-        if (stage.ptr) dev_free(c, stage, false);
-        if (st == VR_OK) st = st2;
-        if (st != VR_OK) {
-            cleanup();
-            return st;
-        }
+        vr_status st = hip_check(hipSetDevice(c->device), "hipSetDevice");
+        if (st != VR_OK) return st;
+        hipStream_t s = (hipStream_t)hip_stream;
+        std::unique_ptr<Cube> cube(new Cube());
+        st = cube_geometry(cube.get(), nx, ny, nz, storage, 1.0);
+        if (st != VR_OK) return st;
+        st = make_room(c, cube->need_bytes(), nullptr, true, {});
+        if (st == VR_EBUSY) st = VR_ENOMEM;
+        if (st != VR_OK) return st;
+        st = cube_fill(c, cube.get(), src, VR_F32, src_on_device, s, channel_divisor);
+        if (st != VR_OK) return st;
         cube->id = c->next_cube++;
         *out = cube->id;
         c->cubes[cube->id] = std::move(cube);
@@ -993,6 +1313,13 @@ vr_status vr_cube_get_info(vr_ctx ctx, vr_cube cube, vr_cube_info* out) {
         out->pool = cu->pool.ptr;
         out->x_chunks = cu->xch;
         out->cell_minmax = (const float*)cu->cellmm.ptr;
+        out->resident = cu->resident ? 1 : 0;
+        out->registered = cu->host_src ? 1 : 0;
+        if (!cu->resident) {
+            out->pool_bytes = (uint64_t)cu->nslots * cu->stride;
+            out->vmin = out->vmax = __builtin_nanf("");
+            return VR_OK;
+        }
         (void)hipSetDevice(c->device);
         std::vector<float> mm((size_t)cu->nslots * 2 * VR_CELLS_PER_BRICK);
         vr_status st = hip_check(hipMemcpy(mm.data(), cu->cellmm.ptr, mm.size() * 4,
@@ -1108,6 +1435,8 @@ vr_status vr_render(vr_ctx ctx, vr_cube cube, const vr_render_params* params, vo
         st = hip_check(hipSetDevice(c->device), "hipSetDevice");
         if (st != VR_OK) return st;
         hipStream_t s = (hipStream_t)hip_stream;
+        st = ensure_resident(c, cu, s, true, {});
+        if (st != VR_OK) return st;
         DevReq R;
         MaskEntry* me = nullptr;
         c->launch_stamp = c->mask_stamp;

@@ -21,12 +21,35 @@ struct ff {
 #define VR_BRICK_APRON 33           // stored edge: brick plus one apron voxel
 #define VR_CELL 8                   // skip-cell edge (voxels)
 #define VR_CELLS_PER_BRICK 64       // 4 x 4 x 4
+// Render workgroups: VR_WG threads own a VR_TW x VR_TH pixel tile, one 8x8
+// block per wave, and VR_WG_PER_CU of them share a compute unit's LDS.
+#ifndef VR_TW
 #define VR_TW 32                    // workgroup tile width (pixels)
+#endif
+#ifndef VR_TH
 #define VR_TH 16                    // workgroup tile height (pixels)
-#define VR_WG 512                   // threads per render workgroup (8 waves of 64)
+#endif
+#define VR_WG (VR_TW * VR_TH)       // threads per render workgroup (one per pixel)
 #define VR_NWAVE (VR_WG / 64)
-#define VR_LDS_MAX 163840           // LDS per workgroup on gfx950
+#ifndef VR_WG_PER_CU
+#define VR_WG_PER_CU 1              // render workgroups resident per compute unit
+#endif
+#define VR_LDS_CU 163840            // LDS per compute unit on gfx950
+#define VR_LDS_MAX (VR_LDS_CU / VR_WG_PER_CU)  // LDS per render workgroup
 #define VR_LDS_STATIC 4096          // reserved for the kernels' static LDS
+// Slab boxes are sized against this many bytes (per buffer, two buffers),
+// whatever LDS a launch actually leaves free, so that the image never depends
+// on it; it fits beside a 256-row transfer function.
+#ifndef VR_BOX_REF
+#define VR_BOX_REF (VR_WG_PER_CU == 1 ? 73728 : (VR_LDS_MAX - VR_LDS_STATIC - 32 * 256) / 32 * 16)
+#endif
+// MIP running-maximum skipping keeps, per slab box, one bound per 8^3 cell in
+// LDS (three slabs in flight) where the transfer function would otherwise sit.
+#define VR_MIPC (768 / VR_WG_PER_CU)          // cells per slab box
+#define VR_MIPC_BYTES (3 * VR_MIPC * 4)
+#define VR_TROW 16                            // cells per box row (longer rows: no skipping)
+// Waves of the render kernels per SIMD (what the register budget must allow).
+#define VR_WAVES_PER_EU ((VR_NWAVE * VR_WG_PER_CU + 3) / 4)
 // Brick slot layout.  A slot stores local voxels x in [0, 4*xch), y in [0, 36),
 // z in [0, 34) (the brick's 33^3 with its apron, padded), each the
 // edge-clamped value of its global position.  Memory is cut into 128-byte
@@ -47,6 +70,9 @@ struct DevCube {
     const uint8_t* pool;            // brick slots
     const uint64_t* mask;           // per slot: bit c set if cell c may contribute
     const uint32_t* cellbits;       // per cell (x fastest, 4 cells per brick edge): may contribute
+    const float* cellmax;           // MIP, per cell in the same order: a bound on every value its
+                                    // samples can take if the cell can reach the clip, else -inf
+                                    // (NULL: no running-maximum skipping)
     uint64_t stride;                // bytes per slot
     int32_t nx, ny, nz;
     int32_t bx, by, bz;             // bricks per axis

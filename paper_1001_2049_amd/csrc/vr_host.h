@@ -40,6 +40,7 @@ struct Uses {
     vr_status record(hipStream_t s);        // after the work just enqueued on s
     vr_status wait_on(hipStream_t s) const; // make s wait for every recorded use
     vr_status sync() const;                 // the host waits for every recorded use
+    bool done() const;                      // every recorded use has completed (no wait)
     void destroy();
 };
 
@@ -49,6 +50,7 @@ struct MaskEntry {
     uint32_t clip_bits = 0;
     DevBuf buf;                     // per slot 64-bit masks
     DevBuf bits;                    // per-cell grid
+    DevBuf cellmax;                 // MIP: per-cell running-maximum bounds (grid order)
     hipEvent_t ready = nullptr;     // recorded after the classification that filled it
     Uses uses;                      // work reading it
     uint64_t stamp = 0;
@@ -67,7 +69,15 @@ struct Cube {
     std::deque<MaskEntry> masks;    // deque: entries never move while requests point at them
     Uses uses;                      // work reading this cube
     int refs = 0;                   // queued serving requests
+    // Cubes registered with a host source are admitted to device memory on
+    // demand and may be evicted while idle; uploaded cubes stay resident.
+    const void* host_src = nullptr; // caller-owned voxels (registered cubes)
+    int src_dtype = VR_F32;
+    bool resident = false;
+    int pins = 0;                   // served requests that have started on it
+    uint64_t lru = 0;               // last admission or use, in ctx->lru_clock ticks
     uint64_t bytes() const;
+    uint64_t need_bytes() const;    // device bytes of its pool and statistics
 };
 
 struct Tf {
@@ -118,6 +128,8 @@ struct Ctx {
     int32_t next_cube = 1, next_tf = 1;
     int64_t next_tf_version = 1;
     uint64_t mask_stamp = 0;
+    uint64_t lru_clock = 0;
+    uint64_t uploads = 0, evictions = 0;  // on-demand admissions of registered cubes
     uint64_t launch_stamp = 0;  // mask_stamp when the current launch began: newer entries are in use
 
     // scratch for single renders / batches
@@ -159,6 +171,17 @@ vr_status build_request(Ctx* c, Cube* cube, Tf* tf, float clip, const vr_camera&
 vr_status mark_use(Ctx* c, Cube* cube, Tf* tf, MaskEntry* mask, hipStream_t s);
 
 Cube* find_cube(Ctx* c, vr_cube id);
+
+// Make a cube's voxels resident on the device.  A registered cube that is not
+// resident is uploaded from its host source after evicting idle registered
+// cubes, least recently used first, until it fits the budget.  Cubes in
+// `keep` (those of the launch being formed) are never evicted.  may_wait:
+// wait for an idle candidate's queued work before evicting it; otherwise a
+// candidate with work in flight is passed over.  Returns VR_EBUSY when the
+// cube cannot be admitted now but might be once work completes, VR_ENOMEM
+// when it cannot be admitted at all.
+vr_status ensure_resident(Ctx* c, Cube* cube, hipStream_t s, bool may_wait,
+                          const std::vector<Cube*>& keep);
 Tf* find_tf(Ctx* c, vr_tf id);
 
 // one persistent launch over many requests (used by vr_render_batch and the server);

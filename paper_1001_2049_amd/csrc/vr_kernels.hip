@@ -39,7 +39,7 @@ template <int SRC, int DST>
 __global__ __launch_bounds__(VR_BB_WG) void k_brick_build(
     const void* __restrict__ src, int64_t nx, int64_t ny, int64_t nz, int64_t z_first, int bz,
     int Bx, int By, uint8_t* __restrict__ pool, uint64_t stride, int xch,
-    float* __restrict__ cell_minmax, float sigma) {
+    float* __restrict__ cell_minmax, float sigma, const float* __restrict__ zdiv) {
     __shared__ float vals[VR_BRICK_VOX];
     __shared__ float cmin[VR_CELLS_PER_BRICK], cmax[VR_CELLS_PER_BRICK];
     const int bxi = blockIdx.x % Bx, byi = blockIdx.x / Bx;
@@ -62,17 +62,19 @@ __global__ __launch_bounds__(VR_BB_WG) void k_brick_build(
         const int64_t si = ((gz - z_first) * ny + gy) * nx + gx;
         float dec;
         if (SRC == 0) {
+            // stored value: v / sigma, or v / zdiv[z] with per-channel divisors
             const float v = ((const float*)src)[si];
+            const float d = zdiv ? zdiv[gz] : sigma;
             if (DST == 0) {
-                const float sv = v / sigma;
+                const float sv = v / d;
                 ((float*)dst)[e] = sv;
                 dec = sv;
             } else if (DST == 1) {
-                const uint16_t c = enc_f16(v / sigma);
+                const uint16_t c = enc_f16(v / d);
                 ((uint16_t*)dst)[e] = c;
                 dec = Vox<1>::dec(c);
             } else {
-                const uint16_t c = enc_bf16(v / sigma);
+                const uint16_t c = enc_bf16(v / d);
                 ((uint16_t*)dst)[e] = c;
                 dec = Vox<2>::dec(c);
             }
@@ -295,20 +297,20 @@ __global__ void k_reset_head(unsigned* head) {
 template <int SRC, int DST>
 static hipError_t launch_bb(const void* src, int64_t nx, int64_t ny, int64_t nz, int64_t z_first,
                             int bz, int Bx, int By, uint8_t* pool, uint64_t stride, int xch,
-                            float* cell_minmax, float sigma, hipStream_t s) {
+                            float* cell_minmax, float sigma, const float* zdiv, hipStream_t s) {
     hipLaunchKernelGGL((k_brick_build<SRC, DST>), dim3(Bx * By), dim3(VR_BB_WG), 0, s, src, nx,
-                       ny, nz, z_first, bz, Bx, By, pool, stride, xch, cell_minmax, sigma);
+                       ny, nz, z_first, bz, Bx, By, pool, stride, xch, cell_minmax, sigma, zdiv);
     return hipGetLastError();
 }
 
 hipError_t vr_launch_brick_build(int src_kind, int dst, const void* src, int64_t nx, int64_t ny,
                                  int64_t nz, int64_t z_first, int bz, int Bx, int By,
                                  uint8_t* pool, uint64_t stride, int xch, float* cell_minmax,
-                                 float sigma, hipStream_t s) {
+                                 float sigma, const float* zdiv, hipStream_t s) {
 #define VR_BB(S, D)                                                                          \
     if (src_kind == S && dst == D)                                                           \
         return launch_bb<S, D>(src, nx, ny, nz, z_first, bz, Bx, By, pool, stride, xch,      \
-                               cell_minmax, sigma, s);
+                               cell_minmax, sigma, zdiv, s);
     VR_BB(0, 0)
     VR_BB(0, 1)
     VR_BB(0, 2)
@@ -318,9 +320,34 @@ hipError_t vr_launch_brick_build(int src_kind, int dst, const void* src, int64_t
     return hipErrorInvalidValue;
 }
 
+// MIP running-maximum bounds, one per cell in the cell-grid order.  A sample
+// in a cell is a trilinear (or nearest) combination of values in [mn, mx]
+// (the cell's halo-inclusive range), rounded at each of three lerps; each lerp
+// can exceed the larger of its operands by at most about 3 u M (u = 2^-24,
+// M = max(|mn|, |mx|)), so every such value lies below mx + 10 u M.  The bound
+// adds 2^-19 M (32 u M, still > 30 u M after its own rounding) and a tiny
+// absolute term.  A running maximum m >= bound can therefore not be raised by
+// any sample of the cell.  Cells entirely below the clip get -inf: under the
+// clip floor they never decide the output.
+__global__ __launch_bounds__(VR_BB_WG) void k_cellmax(const float* __restrict__ cell_minmax,
+                                                      float* __restrict__ cellmax, int64_t ncells,
+                                                      int Bx, int By, float clip) {
+    const int64_t i = (int64_t)blockIdx.x * VR_BB_WG + threadIdx.x;
+    if (i >= ncells) return;
+    const int64_t Cx = 4 * (int64_t)Bx, Cy = 4 * (int64_t)By;
+    const int cx = (int)(i % Cx), cy = (int)((i / Cx) % Cy);
+    const int64_t cz = i / (Cx * Cy);
+    const uint64_t slot = ((uint64_t)(cz >> 2) * By + (cy >> 2)) * Bx + (cx >> 2);
+    const int c = (int)(((cz & 3) * 4 + (cy & 3)) * 4 + (cx & 3));
+    const float mn = cell_minmax[slot * (2 * VR_CELLS_PER_BRICK) + 2 * c];
+    const float mx = cell_minmax[slot * (2 * VR_CELLS_PER_BRICK) + 2 * c + 1];
+    const float M = fmaxf(fabsf(mn), fabsf(mx));
+    cellmax[i] = mx < clip ? -VR_INF : mx + (M * 0x1p-19f + 1e-30f);
+}
+
 hipError_t vr_launch_classify(const float* cell_minmax, uint64_t* mask, uint32_t* cellbits,
-                              int Bx, int By, int Bz, int mode, float clip, float scale,
-                              float bias, int n, const int* kpos, hipStream_t s) {
+                              float* cellmax, int Bx, int By, int Bz, int mode, float clip,
+                              float scale, float bias, int n, const int* kpos, hipStream_t s) {
     const int nslots = Bx * By * Bz;
     if (nslots <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_classify, dim3((nslots + VR_BB_WG - 1) / VR_BB_WG), dim3(VR_BB_WG), 0, s,
@@ -330,6 +357,11 @@ hipError_t vr_launch_classify(const float* cell_minmax, uint64_t* mask, uint32_t
     const int nwords = vr_cellbits_words(Bx, By, Bz);
     hipLaunchKernelGGL(k_cellbits, dim3((nwords + VR_BB_WG - 1) / VR_BB_WG), dim3(VR_BB_WG), 0, s,
                        (const uint64_t*)mask, cellbits, nwords, Bx, By);
+    e = hipGetLastError();
+    if (e != hipSuccess || mode != 1 || !cellmax) return e;
+    const int64_t ncells = (int64_t)nslots * VR_CELLS_PER_BRICK;
+    hipLaunchKernelGGL(k_cellmax, dim3((unsigned)((ncells + VR_BB_WG - 1) / VR_BB_WG)), dim3(VR_BB_WG), 0,
+                       s, cell_minmax, cellmax, ncells, Bx, By, clip);
     return hipGetLastError();
 }
 

@@ -12,24 +12,39 @@ inline int vr_cellbits_words(int Bx, int By, int Bz) {
     return (int)((cells + 31) / 32);
 }
 
-// LDS bytes of one slab box buffer for a transfer function of n rows (0: MIP)
+// LDS bytes reserved ahead of the slab boxes: the transfer function (EA, n
+// rows of 32 bytes) or the cell bounds of MIP running-maximum skipping.
+inline int vr_lds_reserve(int tf_rows) {
+    return 32 * tf_rows > VR_MIPC_BYTES ? 32 * tf_rows : VR_MIPC_BYTES;
+}
+
+// LDS bytes of one slab box buffer beside a transfer function of n rows (0: MIP)
 inline int vr_box_bytes(int tf_rows) {
-    const int avail = (VR_LDS_MAX - VR_LDS_STATIC - 32 * tf_rows) / 2;
+    const int avail = (VR_LDS_MAX - VR_LDS_STATIC - vr_lds_reserve(tf_rows)) / 2;
     const int b = (avail / 16) * 16;
-    return b < 73728 ? b : 73728;
+    return b < VR_BOX_REF ? b : VR_BOX_REF;
 }
 
 // Build the bricks of brick layer bz from a linear slab whose first plane is
 // z_first.  src_kind: 0 float32 values, 1/2 16-bit codes stored as-is.
+// Float32 values are divided by sigma, or by zdiv[z] (device, one per plane)
+// when zdiv is not NULL.
 hipError_t vr_launch_brick_build(int src_kind, int dst, const void* src, int64_t nx, int64_t ny,
                                  int64_t nz, int64_t z_first, int bz, int Bx, int By,
                                  uint8_t* pool, uint64_t stride, int xch, float* cell_minmax,
-                                 float sigma, hipStream_t s);
+                                 float sigma, const float* zdiv, hipStream_t s);
+
+// Robust noise of `planes` channels (z planes of `plane` floats each, the first
+// being plane z_first of the cube) into med/mad/sigma[z] (device arrays).
+hipError_t vr_launch_channel_noise(const float* src, int64_t plane, int64_t z_first, int planes,
+                                   float* med, float* mad, float* sigma, hipStream_t s);
 
 // Skip masks (per slot) and the per-cell grid for one (mode, transfer function, clip).
+// With mode 1 (MIP) and cellmax != NULL also the per-cell bounds of running-
+// maximum skipping (see DevCube::cellmax).
 hipError_t vr_launch_classify(const float* cell_minmax, uint64_t* mask, uint32_t* cellbits,
-                              int Bx, int By, int Bz, int mode, float clip, float scale,
-                              float bias, int n, const int* kpos, hipStream_t s);
+                              float* cellmax, int Bx, int By, int Bz, int mode, float clip,
+                              float scale, float bias, int n, const int* kpos, hipStream_t s);
 
 // One image, one workgroup per 32x16 tile, dispatched most expensive tile
 // first.  order: device scratch of tiles_x * tiles_y ints; hist: 256 words.

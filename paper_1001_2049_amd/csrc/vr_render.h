@@ -287,8 +287,8 @@ __device__ __forceinline__ void store_pixel(const DevReq& R, int px, int py, boo
 
 __device__ __forceinline__ void tile_pixel(const DevReq& R, int tx, int ty, int& px, int& py) {
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    px = tx * VR_TW + (wave & 3) * 8 + (lane & 7);
-    py = ty * VR_TH + (wave >> 2) * 8 + (lane >> 3);
+    px = tx * VR_TW + (wave % (VR_TW / 8)) * 8 + (lane & 7);
+    py = ty * VR_TH + (wave / (VR_TW / 8)) * 8 + (lane >> 3);
 }
 
 // ---------------------------------------------------------------------------
@@ -439,9 +439,10 @@ __device__ __forceinline__ void render_lane_direct(const DevReq& R, const int px
 // the brick pool with the same arithmetic.
 // ---------------------------------------------------------------------------
 #define VR_BIG 0x3fffffff
+#ifndef VR_PAIR_FETCH
+#define VR_PAIR_FETCH 0
+#endif
 #define VR_SMAX 32
-// boxes are sized against this many bytes whatever LDS is actually free
-#define VR_BOX_REF 73728
 
 
 __device__ __forceinline__ int wave_min(int v) {
@@ -790,6 +791,49 @@ __device__ __forceinline__ bool tile_march(const DevReq& R, const Ray& ray, cons
         }
         if (add) atomicAdd(&sh.nact[k & 7], add);
     };
+    // MIP running-maximum skipping: the bound of each of the box's 8^3 cells
+    // (DevCube::cellmax) is kept in LDS, three slabs in flight like the cell
+    // rows; one thread per row of cells along x loads them two slabs ahead.
+    // Boxes with rows longer than VR_TROW cells or more than VR_MIPC cells are
+    // sampled without it.
+    float* const cthr = MODE == 1 ? const_cast<float*>(tfl) : nullptr;
+    auto thr_ok = [&](const Slab& s) -> bool {
+        if (MODE != 1 || !R.use_skip || !R.cube.cellmax || s.S == 0 || s.elems == 0) return false;
+        const int nxc = ((s.lo[0] + s.dim[0] - 2) >> 3) - (s.lo[0] >> 3) + 1;
+        const int nyc = ((s.lo[1] + s.dim[1] - 2) >> 3) - (s.lo[1] >> 3) + 1;
+        const int nzc = ((s.lo[2] + s.dim[2] - 2) >> 3) - (s.lo[2] >> 3) + 1;
+        return nxc <= VR_TROW && nyc * nzc <= VR_WG && nxc * nyc * nzc <= VR_MIPC;
+    };
+    struct Thr {
+        float v[MODE == 1 ? VR_TROW : 1];
+        int row, nxc;
+    };
+    auto thr_issue = [&](const Slab& s) -> Thr {
+        Thr t;
+        t.row = -1;
+        t.nxc = 0;
+        if (MODE != 1 || !thr_ok(s)) return t;
+        const int c0x = s.lo[0] >> 3, c0y = s.lo[1] >> 3, c0z = s.lo[2] >> 3;
+        const int nxc = ((s.lo[0] + s.dim[0] - 2) >> 3) - c0x + 1;
+        const int nyc = ((s.lo[1] + s.dim[1] - 2) >> 3) - c0y + 1;
+        const int nrow = nyc * (((s.lo[2] + s.dim[2] - 2) >> 3) - c0z + 1);
+        t.nxc = nxc;
+        if (tid >= nrow) return t;
+        const int czr = div_small(tid, nyc, 1.0f / (float)nyc);
+        const int64_t b0 = ((int64_t)(c0z + czr) * Cy + (c0y + tid - czr * nyc)) * Cx + c0x;
+#pragma unroll
+        for (int i = 0; i < (MODE == 1 ? VR_TROW : 1); ++i)
+            t.v[i] = i < nxc ? R.cube.cellmax[b0 + i] : -VR_INF;
+        t.row = tid;
+        return t;
+    };
+    auto thr_done = [&](int k, const Thr& t) {
+        if (MODE != 1 || t.row < 0) return;
+        float* dst = cthr + (k % 3) * VR_MIPC + t.row * t.nxc;
+#pragma unroll
+        for (int i = 0; i < (MODE == 1 ? VR_TROW : 1); ++i)
+            if (i < t.nxc) dst[i] = t.v[i];
+    };
     // Copy a slab's box into its LDS buffer: the box is row-major over
     // [z][y][16-byte chunk] with np chunks per row and planes box_plane()
     // elements apart, and global->LDS loads write 16 bytes per lane at
@@ -883,6 +927,8 @@ __device__ __forceinline__ bool tile_march(const DevReq& R, const Ray& ray, cons
     if (R.use_skip) {
         bits_done(0, bits_issue(s0));
         bits_done(1, bits_issue(s1));
+        thr_done(0, thr_issue(s0));
+        thr_done(1, thr_issue(s1));
         __syncthreads();
     }
     if (sh.any[0]) box_dma(s0);
@@ -901,6 +947,7 @@ __device__ __forceinline__ bool tile_march(const DevReq& R, const Ray& ray, cons
         const Slab s2 = sh.ring[(it + 2) & 3];
         Bits bb = {0u, 0u, 0u, 0u, 0, -1, 0, 0};
         if (R.use_skip) bb = bits_issue(s2);
+        const Thr th = thr_issue(s2);
         if (!s1.late && sh.any[(it + 1) & 7]) box_dma(s1);
         const int ke1 = slab_end(s1, ke0);
         // ---- sample slab it
@@ -946,7 +993,9 @@ __device__ __forceinline__ bool tile_march(const DevReq& R, const Ray& ray, cons
                 }
                 const int nyc = cb1[1] - cb0[1] + 1;
                 const unsigned ncell = (unsigned)((cb1[0] - cb0[0] + 1) * nyc * (cb1[2] - cb0[2] + 1));
-                const bool fine = R.use_skip && 4u * (unsigned)__builtin_amdgcn_readfirstlane((int)sh.nact[it & 7]) <= ncell;
+                // MIP: passing over samples that cannot raise the running maximum
+                const bool use_thr = thr_ok(s0);
+                const bool fine = use_thr || (R.use_skip && 4u * (unsigned)__builtin_amdgcn_readfirstlane((int)sh.nact[it & 7]) <= ncell);
                 const uint64_t* crow = sh.crow[it % 3];
                 auto live = [&](int j) -> bool {
                     const float ja = (float)j - 0.5f, jb = (float)j + 7.0f;
@@ -968,17 +1017,60 @@ __device__ __forceinline__ bool tile_march(const DevReq& R, const Ray& ray, cons
                             hit |= crow[(cz - cb0[2]) * nyc + (cy - cb0[1])];
                     return (hit & xm) != 0ull;
                 };
-                auto run = [&](auto fetch, auto chunked) {
+                // MIP: some cell the samples j .. j+7 can touch has a bound above
+                // the running maximum (bounds are -inf for cells below the clip)
+                const int nxc = cb1[0] - cb0[0] + 1;
+                const float* cth = MODE == 1 ? cthr + (it % 3) * VR_MIPC : nullptr;
+                auto live_max = [&](int j) -> bool {
+                    const float ja = (float)j - 0.5f, jb = (float)j + 7.0f;
+                    int c_lo[3], c_hi[3];
+#pragma unroll
+                    for (int a = 0; a < 3; ++a) {
+                        const float qa = __builtin_amdgcn_fmed3f(__builtin_fmaf(ja, ray.dd[a], A[a]), 0.0f, ch[a]);
+                        const float qb = __builtin_amdgcn_fmed3f(__builtin_fmaf(jb, ray.dd[a], A[a]), 0.0f, ch[a]);
+                        const int ia = INTERP == 1 ? (int)qa : (int)(qa + 0.5f);
+                        const int ib = INTERP == 1 ? (int)qb : (int)(qb + 0.5f);
+                        c_lo[a] = min(max((s0.lo[a] + min(ia, ib)) >> 3, cb0[a]), cb1[a]) - cb0[a];
+                        c_hi[a] = min(max((s0.lo[a] + max(ia, ib)) >> 3, cb0[a]), cb1[a]) - cb0[a];
+                    }
+                    float t = -VR_INF;
+                    for (int cz = c_lo[2]; cz <= c_hi[2]; ++cz)
+                        for (int cy = c_lo[1]; cy <= c_hi[1]; ++cy) {
+                            const float* rowp = cth + (cz * nyc + cy) * nxc;
+                            for (int cx = c_lo[0]; cx <= c_hi[0]; ++cx) t = fmaxf(t, rowp[cx]);
+                        }
+                    return t > acc.m;
+                };
+                auto run = [&](auto fetch, auto fetch2, auto chunked) {
                     const int jl = ray.n - 1 - ks;  // index of the ray's last sample in this slab, if any
                     int j = 0;
                     for (; j + 1 < cnt_s; j += 2) {
-                        if (decltype(chunked)::value && (j & 7) == 0 && __ballot(live(j)) == 0ull) {
+                        if (decltype(chunked)::value && (j & 7) == 0 &&
+                            __ballot(MODE == 1 && use_thr ? live_max(j) : live(j)) == 0ull) {
                             nskip += (unsigned)min(8, cnt_s - j);
                             j += 6;
                             continue;
                         }
+#if VR_PAIR_FETCH
+                        float v0, v1;
+                        {
+                            const float ja = (float)j, jb = (float)(j + 1) + (j + 1 == jl ? ray.last_adj : 0.0f);
+                            const float pa[3] = {__builtin_fmaf(ja, ray.dd[0], A[0]),
+                                                 __builtin_fmaf(ja, ray.dd[1], A[1]),
+                                                 __builtin_fmaf(ja, ray.dd[2], A[2])};
+                            const float pb[3] = {__builtin_fmaf(jb, ray.dd[0], A[0]),
+                                                 __builtin_fmaf(jb, ray.dd[1], A[1]),
+                                                 __builtin_fmaf(jb, ray.dd[2], A[2])};
+                            int ia[3], ib[3];
+                            float wa[3], wb[3];
+                            floor_idx<INTERP>(pa, ch, ia, wa);
+                            floor_idx<INTERP>(pb, ch, ib, wb);
+                            fetch2(ia, wa, ib, wb, v0, v1);
+                        }
+#else
                         const float v0 = value(fetch, j, false);
                         const float v1 = value(fetch, j + 1, j + 1 == jl);
+#endif
                         if (MODE == 1) {
                             nexec += 2;
                             acc.m = fmaxf(acc.m, fmaxf(v0, v1));
@@ -1017,23 +1109,46 @@ __device__ __forceinline__ bool tile_march(const DevReq& R, const Ray& ray, cons
                         }
                         return trilerp(cc[0], cc[1], cc[2], cc[3], cc[4], cc[5], cc[6], cc[7], w[0], w[1], w[2]);
                     };
+                    // two samples at once: both corner sets are read with one wait
+                    auto fetch2 = [&](const int* ia, const float* wa, const int* ib, const float* wb,
+                                      float& va, float& vb) {
+                        const int sk = box_skew<M, CV>();
+                        const int ja = (int)__umul24(__umul24(ia[2], s0.dim[1]) + ia[1], pitch) + ia[0] + xoff + ia[2] * sk;
+                        const int jb = (int)__umul24(__umul24(ib[2], s0.dim[1]) + ib[1], pitch) + ib[0] + xoff + ib[2] * sk;
+                        if (INTERP == 0) {
+                            va = Vox<DT>::dec(box[ja]);
+                            vb = Vox<DT>::dec(box[jb]);
+                            return;
+                        }
+                        float ca[8], cb[8];
+                        box_corners<DT>(box, ja, sy, sz, ca);
+                        box_corners<DT>(box, jb, sy, sz, cb);
+                        va = trilerp(ca[0], ca[1], ca[2], ca[3], ca[4], ca[5], ca[6], ca[7], wa[0], wa[1], wa[2]);
+                        vb = trilerp(cb[0], cb[1], cb[2], cb[3], cb[4], cb[5], cb[6], cb[7], wb[0], wb[1], wb[2]);
+                    };
                     if (fine)
-                        run(fetch, BoolC<true>());
+                        run(fetch, fetch2, BoolC<true>());
                     else
-                        run(fetch, BoolC<false>());
+                        run(fetch, fetch2, BoolC<false>());
                 } else {
                     auto fetch = [&](const int* i, const float* w) {
                         return pool_value<DT, INTERP>(R.cube, s0.lo[0] + i[0], s0.lo[1] + i[1],
                                                       s0.lo[2] + i[2], w[0], w[1], w[2]);
                     };
+                    auto fetch2 = [&](const int* ia, const float* wa, const int* ib, const float* wb,
+                                      float& va, float& vb) {
+                        va = fetch(ia, wa);
+                        vb = fetch(ib, wb);
+                    };
                     if (fine)
-                        run(fetch, BoolC<true>());
+                        run(fetch, fetch2, BoolC<true>());
                     else
-                        run(fetch, BoolC<false>());
+                        run(fetch, fetch2, BoolC<false>());
                 }
             }
         }
         if (R.use_skip) bits_done(it + 2, bb);
+        thr_done(it + 2, th);
         const bool done = !act || stopped || ke0 >= ray.n;
         if (__ballot(!done) != 0ull && lane == 0) sh.alive[it % 3] = 1;
         if (s1.late) {  // the box of slab it + 1 needs the LDS slab it used
@@ -1149,13 +1264,14 @@ __device__ __forceinline__ void flush_counts(const LaneCounts& c, DevCounters* c
 
 // dynamic LDS: transfer-function rows (n x 32 bytes), then two slab boxes
 template <int MODE, int DT, int INTERP>
-__global__ __launch_bounds__(VR_WG) void k_render(const DevReq R, const int* __restrict__ order,
+__global__ __launch_bounds__(VR_WG, VR_WAVES_PER_EU) void k_render(const DevReq R, const int* __restrict__ order,
                                                    DevCounters* cnt) {
     extern __shared__ float4 lds4[];
     __shared__ unsigned wgc[5];
     __shared__ TileShared sh;
     float* tfl = (float*)lds4;
-    const int tf_bytes = MODE == 0 ? 32 * R.tf.n : 0;
+    // EA: transfer-function rows; MIP: cell bounds of running-maximum skipping
+    const int tf_bytes = MODE == 0 ? 32 * R.tf.n : VR_MIPC_BYTES;
     if (MODE == 0) {
         const float4* rows = (const float4*)R.tf.rows;
         for (int e = threadIdx.x; e < 2 * R.tf.n; e += VR_WG) lds4[e] = rows[e];
@@ -1181,7 +1297,7 @@ static inline hipError_t check_lds(const void* kernel, size_t dynamic_bytes) {
 template <int MODE, int DT, int INTERP>
 static hipError_t launch_r(const DevReq& R, const int* order, DevCounters* cnt, hipStream_t s) {
     const int grid = R.tiles_x * R.tiles_y;
-    const size_t lds = (MODE == 0 ? (size_t)R.tf.n * 32 : 0) + 2 * (size_t)R.box_bytes;
+    const size_t lds = (MODE == 0 ? (size_t)R.tf.n * 32 : (size_t)VR_MIPC_BYTES) + 2 * (size_t)R.box_bytes;
     const hipError_t e = check_lds((const void*)k_render<MODE, DT, INTERP>, lds);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL((k_render<MODE, DT, INTERP>), dim3(grid), dim3(VR_WG), lds, s, R, order, cnt);

@@ -5,7 +5,7 @@
 template <int MODE, int DT>
 __device__ __forceinline__ void dispatch_interp(const DevReq& R, int tx, int ty, float* tfl,
                                                 TileShared& sh, LaneCounts& c) {
-    uint8_t* boxes = (uint8_t*)tfl + (MODE == 0 ? 32 * R.tf.n : 0);
+    uint8_t* boxes = (uint8_t*)tfl + (MODE == 0 ? 32 * R.tf.n : VR_MIPC_BYTES);
     if (R.interp == 1) render_tile_any<MODE, DT, 1>(R, tx, ty, tfl, boxes, sh, c);
     else render_tile_any<MODE, DT, 0>(R, tx, ty, tfl, boxes, sh, c);
 }
@@ -20,7 +20,7 @@ __device__ __forceinline__ void dispatch_dtype(const DevReq& R, int tx, int ty, 
 
 // Persistent grid: each workgroup pulls (request, tile) items until the list is
 // exhausted.  Which workgroup renders a tile never changes the tile's pixels.
-__global__ __launch_bounds__(VR_WG) void k_render_batch(const DevReq* __restrict__ reqs,
+__global__ __launch_bounds__(VR_WG, VR_WAVES_PER_EU) void k_render_batch(const DevReq* __restrict__ reqs,
                                                         const DevItem* __restrict__ items,
                                                         const int* __restrict__ nitems_p,
                                                         unsigned* head, DevCounters* cnt) {

@@ -35,6 +35,8 @@ struct Ticket {
     int next_tile = 0;    // tiles [0, next_tile) are assigned to launches
     int outstanding = 0;  // launches in flight holding some of its tiles
     bool done = false;
+    bool pinned = false;  // holds a pin on its cube (admitted, keeps it resident)
+    int bypassed = 0;     // launches formed while it waited for memory
     vr_status status = VR_OK;
     double t_arr = 0.0, t_first = -1.0, t_done = 0.0;
 };
@@ -67,9 +69,18 @@ static int tiles_of(const vr_render_params& p) {
     return ((p.width + VR_TW - 1) / VR_TW) * ((p.height + VR_TH - 1) / VR_TH);
 }
 
+// Launches a request waiting for memory lets pass before the server stops
+// forming launches until the device has drained enough to admit its cube.
+#define VR_MAX_BYPASS 4
+
 // release the cube/TF references of a finished ticket (context lock held)
-static void drop_refs(Ctx* c, const vr_request& r) {
-    if (Cube* cu = find_cube(c, r.cube)) --cu->refs;
+static void drop_refs(Ctx* c, Ticket& tk) {
+    const vr_request& r = tk.req;
+    if (Cube* cu = find_cube(c, r.cube)) {
+        --cu->refs;
+        if (tk.pinned) --cu->pins;
+    }
+    tk.pinned = false;
     if (r.params.mode == VR_EA)
         if (Tf* t = find_tf(c, r.tf)) --t->refs;
 }
@@ -85,7 +96,7 @@ static void fail_all(Server* S, vr_status st, const std::string& msg) {
             kv.second.done = true;
             kv.second.status = st;
             kv.second.t_done = t;
-            drop_refs(S->c, kv.second.req);
+            drop_refs(S->c, kv.second);
         }
     }
     S->pending.clear();
@@ -121,29 +132,74 @@ static void server_loop(Server* S) {
                 if (--tk.outstanding == 0 && tk.next_tile >= tk.ntiles && !tk.done) {
                     tk.done = true;
                     tk.t_done = t;
-                    drop_refs(c, tk.req);
+                    drop_refs(c, tk);
                 }
             }
             sl.tickets.clear();
             sl.busy = false;
             S->cv_done.notify_all();
         }
-        // 2. form launches for free slots from what is queued now
+        // 2. form launches for free slots from what is queued now.  Requests are
+        // taken in arrival order; one whose cube cannot be admitted yet (memory
+        // held by running work) blocks later requests that would need memory,
+        // while requests for resident cubes may pass it, for VR_MAX_BYPASS
+        // launches; after that no request is started until it is admitted.
+        // Requests already started (their cubes pinned) always continue: they
+        // hold the memory the waiting request needs.
         bool launched = false;
+        bool blocked = false;
         for (auto& sl : S->slots) {
             if (sl.busy) continue;
             reqs.clear();
             ranges.clear();
             ids.clear();
+            vr_status dev_err = VR_OK;
             {
+                std::lock_guard<std::recursive_mutex> lkc(c->mu);
                 std::lock_guard<std::mutex> lk(S->m);
                 if (S->pending.empty()) break;
                 int budget = S->cfg.max_batch_tiles;
                 const double t = now_s();
-                while (!S->pending.empty() && budget > 0 &&
+                std::vector<Cube*> keep;
+                Ticket* blocker = nullptr;
+                bool start_none = false;  // the blocker has waited long enough
+                auto itp = S->pending.begin();
+                while (itp != S->pending.end() && budget > 0 &&
                        (int)reqs.size() < S->cfg.max_batch_requests) {
-                    const uint64_t id = S->pending.front();
+                    const uint64_t id = *itp;
                     Ticket& tk = S->tickets[id];
+                    Cube* cube = find_cube(c, tk.req.cube);
+                    if (!tk.pinned) {
+                        if (start_none || (blocker && !cube->resident)) {
+                            ++itp;  // would take memory an older request waits for
+                            continue;
+                        }
+                        const vr_status st = ensure_resident(c, cube, sl.stream, false, keep);
+                        if (st == VR_EBUSY || (st == VR_ENOMEM && !keep.empty())) {
+                            if (!blocker) {
+                                blocker = &tk;
+                                start_none = tk.bypassed >= VR_MAX_BYPASS;
+                            }
+                            ++itp;
+                            continue;
+                        }
+                        if (st == VR_ENOMEM) {  // can never fit beside what must stay resident
+                            tk.done = true;
+                            tk.status = VR_ENOMEM;
+                            tk.t_done = t;
+                            drop_refs(c, tk);
+                            itp = S->pending.erase(itp);
+                            S->cv_done.notify_all();
+                            continue;
+                        }
+                        if (st != VR_OK) {
+                            dev_err = st;
+                            break;
+                        }
+                        ++cube->pins;
+                        tk.pinned = true;
+                    }
+                    if (std::find(keep.begin(), keep.end(), cube) == keep.end()) keep.push_back(cube);
                     const int take = std::min(budget, tk.ntiles - tk.next_tile);
                     reqs.push_back(tk.req);
                     ranges.push_back(tk.next_tile);
@@ -153,21 +209,25 @@ static void server_loop(Server* S) {
                     ++tk.outstanding;
                     if (tk.t_first < 0.0) tk.t_first = t;
                     budget -= take;
-                    if (tk.next_tile >= tk.ntiles) S->pending.pop_front();
+                    if (tk.next_tile >= tk.ntiles) itp = S->pending.erase(itp);
+                    else ++itp;
+                }
+                if (blocker) {
+                    blocked = true;
+                    if (!reqs.empty()) ++blocker->bypassed;
+                }
+                if (dev_err == VR_OK && !reqs.empty()) {
+                    dev_err = launch_requests(c, sl.bb, reqs.data(), (int)reqs.size(), ranges.data(),
+                                              sl.stream, nullptr, S->cfg.use_graphs != 0);
+                    if (dev_err == VR_OK)
+                        dev_err = hip_check(hipEventRecord(sl.ev, sl.stream), "hipEventRecord");
                 }
             }
-            if (reqs.empty()) break;
-            vr_status st;
-            {
-                std::lock_guard<std::recursive_mutex> lkc(c->mu);
-                st = launch_requests(c, sl.bb, reqs.data(), (int)reqs.size(), ranges.data(),
-                                     sl.stream, nullptr, S->cfg.use_graphs != 0);
-                if (st == VR_OK) st = hip_check(hipEventRecord(sl.ev, sl.stream), "hipEventRecord");
-            }
-            if (st != VR_OK) {
-                fail_all(S, st, "launch failed");
+            if (dev_err != VR_OK) {
+                fail_all(S, dev_err, "launch failed: " + std::string(vr_last_error()));
                 return;
             }
+            if (reqs.empty()) break;
             sl.tickets = ids;
             sl.busy = true;
             any_busy = true;
@@ -179,6 +239,9 @@ static void server_loop(Server* S) {
         if (launched) continue;
         if (any_busy) {
             S->cv.wait_for(lk, std::chrono::microseconds(20));
+        } else if (blocked) {
+            // memory is held by work outside the server (renders on other streams)
+            S->cv.wait_for(lk, std::chrono::microseconds(500));
         } else if (S->pending.empty() && !S->stop) {
             S->cv.wait(lk, [&] { return S->stop || !S->pending.empty(); });
         }
@@ -211,7 +274,7 @@ void server_stop(Ctx* c) {
         std::lock_guard<std::mutex> lk(S->m);
         for (auto& kv : S->tickets) {
             if (!kv.second.done) {
-                drop_refs(c, kv.second.req);
+                drop_refs(c, kv.second);
                 kv.second.done = true;
                 kv.second.status = VR_ESTATE;
             }
@@ -346,7 +409,7 @@ vr_status vr_submit(vr_ctx ctx, const vr_request* req, uint64_t* ticket) {
         if (fatal != VR_OK) {
             // lock order is context, then server: take the context lock on its own
             std::lock_guard<std::recursive_mutex> lkc(c->mu);
-            drop_refs(c, tk.req);
+            drop_refs(c, tk);
             set_error("server stopped after: " + fatal_msg);
             return fatal;
         }

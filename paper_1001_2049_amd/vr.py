@@ -68,7 +68,8 @@ class vr_cube_info(ctypes.Structure):
                 ("sigma_scale", ctypes.c_double), ("pool_bytes", ctypes.c_uint64),
                 ("brick_stride", ctypes.c_uint64), ("aux_bytes", ctypes.c_uint64),
                 ("vmin", ctypes.c_float), ("vmax", ctypes.c_float),
-                ("x_chunks", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("x_chunks", ctypes.c_int32), ("resident", ctypes.c_uint8),
+                ("registered", ctypes.c_uint8), ("reserved", ctypes.c_uint16),
                 ("pool", ctypes.c_void_p), ("cell_minmax", ctypes.c_void_p)]
 
 
@@ -76,6 +77,16 @@ class vr_request(ctypes.Structure):
     _fields_ = [("cube", ctypes.c_int32), ("tf", ctypes.c_int32), ("clip", ctypes.c_float),
                 ("reserved", ctypes.c_int32), ("camera", vr_camera),
                 ("params", vr_render_params), ("out_dev", ctypes.c_void_p)]
+
+
+class vr_memory_stats(ctypes.Structure):
+    _fields_ = [("budget_bytes", ctypes.c_uint64), ("used_bytes", ctypes.c_uint64),
+                ("cubes", ctypes.c_uint64), ("resident_cubes", ctypes.c_uint64),
+                ("registered_cubes", ctypes.c_uint64), ("uploads", ctypes.c_uint64),
+                ("evictions", ctypes.c_uint64)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
 
 
 class vr_server_cfg(ctypes.Structure):
@@ -96,6 +107,14 @@ _SIGNATURES = {
     "vr_cube_upload": (S, [P, P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int64, ctypes.c_int64,
                            ctypes.c_int64, ctypes.c_int32, ctypes.c_double, P,
                            ctypes.POINTER(ctypes.c_int32)]),
+    "vr_cube_register": (S, [P, P, ctypes.c_int32, ctypes.c_int64, ctypes.c_int64, ctypes.c_int64,
+                             ctypes.c_int32, ctypes.c_double, ctypes.POINTER(ctypes.c_int32)]),
+    "vr_get_memory_stats": (S, [P, ctypes.POINTER(vr_memory_stats)]),
+    "vr_estimate_channel_noise": (S, [P, P, ctypes.c_int32, ctypes.c_int64, ctypes.c_int64,
+                                      ctypes.c_int64, P, P, P, P]),
+    "vr_cube_upload_scaled": (S, [P, P, ctypes.c_int32, ctypes.c_int64, ctypes.c_int64,
+                                  ctypes.c_int64, ctypes.c_int32, P, P,
+                                  ctypes.POINTER(ctypes.c_int32)]),
     "vr_cube_release": (S, [P, ctypes.c_int32]),
     "vr_cube_get_info": (S, [P, ctypes.c_int32, ctypes.POINTER(vr_cube_info)]),
     "vr_set_transfer_function": (S, [P, P, ctypes.c_int32, ctypes.c_float, ctypes.c_float]),
@@ -240,12 +259,14 @@ class Renderer:
         check(lib().vr_create(device, budget_bytes,
                               ctypes.byref(self._alloc) if self._alloc else None, ctypes.byref(h)))
         self.ctx = h
+        self._host_cubes = {}  # host arrays of registered cubes, alive until release
         _LIVE.add(self)
 
     def close(self):
         if self.ctx:
             check(lib().vr_destroy(self.ctx))
             self.ctx = None
+            self._host_cubes = {}
 
     def __del__(self):
         try:
@@ -293,8 +314,82 @@ class Renderer:
                                    ctypes.byref(out)))
         return out.value
 
+    def register(self, cube, storage="f32", sigma_scale=1.0, src_dtype=None) -> int:
+        """Register a host [nz][ny][nx] cube (numpy float32, or uint16 codes with
+        src_dtype 'f16'/'bf16'; pinned torch CPU tensors also work) for on-demand
+        admission under the context's memory budget.  The array is kept alive
+        here until release."""
+        import numpy as np
+        torch = self._torch
+        if isinstance(cube, torch.Tensor):
+            if cube.is_cuda or not cube.is_contiguous():
+                raise TypeError("register takes a contiguous host array")
+            keep, ptr = cube, cube.data_ptr()
+            dt = {torch.float32: VR_F32, torch.float16: VR_F16,
+                  torch.bfloat16: VR_BF16}.get(cube.dtype)
+            if dt is None:
+                dt = STORAGE[src_dtype]
+        else:
+            keep = np.ascontiguousarray(cube)
+            ptr = keep.ctypes.data
+            if keep.dtype == np.float32:
+                dt = VR_F32
+            elif keep.dtype == np.uint16:
+                dt = STORAGE[src_dtype]
+            else:
+                raise TypeError("cube must be float32 or uint16 codes")
+        nz, ny, nx = keep.shape
+        out = ctypes.c_int32()
+        check(lib().vr_cube_register(self.ctx, ctypes.c_void_p(ptr), dt, nx, ny, nz,
+                                     STORAGE[storage], float(sigma_scale), ctypes.byref(out)))
+        self._host_cubes[out.value] = keep
+        return out.value
+
+    def _f32_source(self, cube):
+        import numpy as np
+        torch = self._torch
+        if isinstance(cube, torch.Tensor):
+            if cube.dtype != torch.float32:
+                raise TypeError("float32 cube required")
+            arr = cube.contiguous()
+            return arr, arr.data_ptr(), int(arr.is_cuda)
+        arr = np.ascontiguousarray(cube, dtype=np.float32)
+        return arr, arr.ctypes.data, 0
+
+    def estimate_channel_noise(self, cube, stream=None):
+        """Per-channel (median, mad, sigma) of a float32 [nz][ny][nx] cube, as
+        three numpy float32 arrays of nz values."""
+        import numpy as np
+        keep, ptr, on_dev = self._f32_source(cube)
+        nz, ny, nx = keep.shape
+        med, mad, sig = (np.empty(nz, np.float32) for _ in range(3))
+        check(lib().vr_estimate_channel_noise(self.ctx, ctypes.c_void_p(ptr), on_dev, nx, ny, nz,
+                                              self._stream(stream), med.ctypes.data,
+                                              mad.ctypes.data, sig.ctypes.data))
+        return med, mad, sig
+
+    def upload_scaled(self, cube, divisors, storage="f32", stream=None) -> int:
+        """Upload a float32 cube storing value / divisors[z] per channel."""
+        import numpy as np
+        keep, ptr, on_dev = self._f32_source(cube)
+        nz, ny, nx = keep.shape
+        d = np.ascontiguousarray(divisors, dtype=np.float32)
+        if d.shape != (nz,):
+            raise ValueError("one divisor per channel required")
+        out = ctypes.c_int32()
+        check(lib().vr_cube_upload_scaled(self.ctx, ctypes.c_void_p(ptr), on_dev, nx, ny, nz,
+                                          STORAGE[storage], d.ctypes.data, self._stream(stream),
+                                          ctypes.byref(out)))
+        return out.value
+
+    def memory_stats(self) -> dict:
+        m = vr_memory_stats()
+        check(lib().vr_get_memory_stats(self.ctx, ctypes.byref(m)))
+        return m.as_dict()
+
     def release(self, cube: int):
         check(lib().vr_cube_release(self.ctx, cube))
+        self._host_cubes.pop(cube, None)
 
     def info(self, cube: int) -> vr_cube_info:
         inf = vr_cube_info()

@@ -153,6 +153,26 @@ def cube(spec: CubeSpec, threads: int | None = None) -> np.ndarray:
     return cube_slab(spec, 0, spec.nz, threads=threads)
 
 
+def band_noise_profile(nz: int) -> np.ndarray:
+    """Noise level per frequency channel for the noise-aware workloads: rising
+    towards the upper band edge (1 -> 1.6) with a narrow interference bump
+    (+0.8 at 30 % of the band, width 5 % of the band)."""
+    z = np.arange(nz, dtype=np.float64)
+    t = z / max(nz - 1, 1)
+    return 1.0 + 0.6 * t * t + 0.8 * np.exp(-((z - 0.3 * nz) / (0.05 * nz)) ** 2)
+
+
+def cube_profiled(spec: CubeSpec, profile: np.ndarray, threads: int | None = None) -> np.ndarray:
+    """Cube whose noise level varies per channel: profile[z] times the unit
+    noise of `spec` plus its sources, rounded once to float32."""
+    import dataclasses
+    prof = np.asarray(profile, dtype=np.float64)
+    assert prof.shape == (spec.nz,)
+    noise = cube(dataclasses.replace(spec, sources=None, sigma=1.0, noise=True), threads)
+    srcs = cube(dataclasses.replace(spec, noise=False), threads)
+    return (prof[:, None, None] * noise.astype(np.float64) + srcs.astype(np.float64)).astype(np.float32)
+
+
 # ----------------------------------------------------------------------------
 # The same generator evaluated on the GPU (for cubes too large to generate on
 # the host in reasonable time).  Source factors are tabulated here with the C

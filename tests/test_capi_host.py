@@ -178,3 +178,24 @@ def test_last_error_is_per_thread(L, ctx):
     assert seen["create"] == vr.VR_EINVAL
     assert seen["msg"] != main_msg
     assert L.vr_last_error() == main_msg
+
+
+def test_register_validation_and_memory_stats(L, ctx):
+    """vr_cube_register validates like vr_cube_upload before touching a device;
+    a host-only context keeps no cubes; memory statistics start empty."""
+    vol = np.zeros((4, 4, 4), np.float32)
+    out = ctypes.c_int32(7)
+    p = vol.ctypes.data
+    assert L.vr_cube_register(ctx, None, vr.VR_F32, 4, 4, 4, vr.VR_F32, 1.0, ctypes.byref(out)) == vr.VR_EINVAL
+    assert out.value == 7 or out.value == 0
+    assert L.vr_cube_register(ctx, p, vr.VR_F32, 1, 4, 4, vr.VR_F32, 1.0, ctypes.byref(out)) == vr.VR_EINVAL
+    assert L.vr_cube_register(ctx, p, vr.VR_F32, 4, 4, 4, 7, 1.0, ctypes.byref(out)) == vr.VR_EINVAL
+    assert L.vr_cube_register(ctx, p, vr.VR_F16, 4, 4, 4, vr.VR_BF16, 1.0,
+                              ctypes.byref(out)) == vr.VR_EUNSUPPORTED
+    assert L.vr_cube_register(ctx, p, vr.VR_F32, 4, 4, 4, vr.VR_F32, 0.0, ctypes.byref(out)) == vr.VR_EINVAL
+    assert L.vr_cube_register(ctx, p, vr.VR_F32, 4, 4, 4, vr.VR_F32, 1.0, ctypes.byref(out)) == vr.VR_EDEVICE
+    assert out.value == 0
+    m = vr.vr_memory_stats()
+    assert L.vr_get_memory_stats(ctx, ctypes.byref(m)) == vr.VR_OK
+    assert m.as_dict() == {k: 0 for k, _ in vr.vr_memory_stats._fields_}
+    assert L.vr_get_memory_stats(ctx, None) == vr.VR_EINVAL
