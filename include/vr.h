@@ -298,6 +298,21 @@ vr_status vr_set_camera(vr_ctx ctx, const vr_camera* cam);
 vr_status vr_render(vr_ctx ctx, vr_cube cube, const vr_render_params* params, void* out_dev,
                     void* hip_stream, vr_stats* stats);
 
+/* For callers that cannot allocate device memory (code under graph capture,
+ * tight serving loops, harnesses that forbid allocation): vr_render without
+ * stats, calling no allocator.  Its dispatch-order scratch is a fixed array of
+ * 1 MiB + 1 KiB in device memory (one per GPU, held until the process ends),
+ * enough for 262144 tiles of 32x16 pixels.  Requires that the cube is
+ * resident and that a vr_render of the same cube (same mode, transfer
+ * function and clip, for its skip mask) already ran on this hip_stream, so
+ * every object it reads is tracked there.  All calls on one GPU share the
+ * scratch: calls that overlap on one GPU (other streams, other contexts)
+ * race.  Images equal vr_render's bit for bit.  Errors: as vr_render;
+ * VR_EINVAL for an image of more tiles than the scratch holds; VR_ESTATE if
+ * the cube, transfer function or skip mask was not prepared on this stream. */
+vr_status vr_render_noalloc(vr_ctx ctx, vr_cube cube, const vr_render_params* params,
+                            void* out_dev, void* hip_stream);
+
 /* --- batched rendering and serving ---------------------------------------- */
 
 /* Transfer functions as objects, for requests that carry their own

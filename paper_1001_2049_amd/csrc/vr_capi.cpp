@@ -57,6 +57,12 @@ vr_status Uses::sync() const {
     return VR_OK;
 }
 
+bool Uses::has(hipStream_t s) const {
+    for (const auto& e : ev)
+        if (e.first == s) return true;
+    return false;
+}
+
 bool Uses::done() const {
     for (const auto& e : ev) {
         const hipError_t q = hipEventQuery(e.second);
@@ -282,7 +288,7 @@ static vr_status ensure_event(hipEvent_t& e) {
 
 // skip mask for (mode, transfer function, clip) on this cube, classified on s if absent
 static vr_status get_mask(Ctx* c, Cube* cube, int mode, Tf* tf, float clip_s, hipStream_t s,
-                          MaskEntry** out) {
+                          MaskEntry** out, bool may_create = true) {
     const int64_t ver = mode == VR_EA ? tf->version : -1;
     uint32_t cb;
     std::memcpy(&cb, &clip_s, 4);
@@ -295,6 +301,11 @@ static vr_status get_mask(Ctx* c, Cube* cube, int mode, Tf* tf, float clip_s, hi
             *out = &m;
             return VR_OK;
         }
+    }
+    if (!may_create) {
+        set_error("the skip mask of this cube, mode, transfer function and clip is not prepared "
+                  "(render it once with vr_render on this stream)");
+        return VR_ESTATE;
     }
     MaskEntry* e = nullptr;
     // evict the least recently used entry that the launch being built does not use
@@ -353,7 +364,7 @@ static vr_status get_mask(Ctx* c, Cube* cube, int mode, Tf* tf, float clip_s, hi
 
 vr_status build_request(Ctx* c, Cube* cube, Tf* tf, float clip, const vr_camera& cam,
                         const vr_render_params& p, void* out, hipStream_t s, DevReq& R,
-                        MaskEntry** mask_used) {
+                        MaskEntry** mask_used, bool prepared_only) {
     std::memset(&R, 0, sizeof(R));
     if (mask_used) *mask_used = nullptr;
     // sample count per ray must stay exactly representable
@@ -399,7 +410,7 @@ vr_status build_request(Ctx* c, Cube* cube, Tf* tf, float clip, const vr_camera&
     R.out_scale = (float)cube->sigma;
     if (p.use_skip) {
         MaskEntry* me = nullptr;
-        vr_status st = get_mask(c, cube, p.mode, tf, clip_s, s, &me);
+        vr_status st = get_mask(c, cube, p.mode, tf, clip_s, s, &me, !prepared_only);
         if (st != VR_OK) return st;
         R.cube.mask = (const uint64_t*)me->buf.ptr;
         R.cube.cellbits = (const uint32_t*)me->bits.ptr;
@@ -982,6 +993,8 @@ vr_status vr_create(int32_t device, uint64_t hbm_budget_bytes, const vr_allocato
             st = hip_check(hipGetDeviceProperties(&prop, device), "hipGetDeviceProperties");
             if (st != VR_OK) return st;
             c->num_cu = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 256;
+            st = noalloc_setup(device);
+            if (st != VR_OK) return st;
         }
         *out = (vr_ctx)c.release();
         return VR_OK;

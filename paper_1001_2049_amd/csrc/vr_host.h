@@ -41,6 +41,7 @@ struct Uses {
     vr_status wait_on(hipStream_t s) const; // make s wait for every recorded use
     vr_status sync() const;                 // the host waits for every recorded use
     bool done() const;                      // every recorded use has completed (no wait)
+    bool has(hipStream_t s) const;          // a use on s has been recorded before
     void destroy();
 };
 
@@ -163,9 +164,13 @@ vr_status check_tf(const float* rgbk, int32_t n, float v0, float v1);
 void camera_setup(const vr_camera& cam, int W, int H, DevCam& out);
 
 // fill a DevReq for one image; classifies the skip mask on `s` if needed
+// (prepared_only: never classify or allocate; VR_ESTATE if the mask is absent)
 vr_status build_request(Ctx* c, Cube* cube, Tf* tf, float clip, const vr_camera& cam,
                         const vr_render_params& p, void* out, hipStream_t s, DevReq& R,
-                        MaskEntry** mask_used);
+                        MaskEntry** mask_used, bool prepared_only = false);
+
+// Allocation-free renders: per-device set-up at context creation.
+vr_status noalloc_setup(int device);
 
 // mark objects used by work enqueued on s
 vr_status mark_use(Ctx* c, Cube* cube, Tf* tf, MaskEntry* mask, hipStream_t s);

@@ -122,6 +122,7 @@ _SIGNATURES = {
     "vr_set_camera": (S, [P, ctypes.POINTER(vr_camera)]),
     "vr_render": (S, [P, ctypes.c_int32, ctypes.POINTER(vr_render_params), P, P,
                       ctypes.POINTER(vr_stats)]),
+    "vr_render_noalloc": (S, [P, ctypes.c_int32, ctypes.POINTER(vr_render_params), P, P]),
     "vr_tf_create": (S, [P, P, ctypes.c_int32, ctypes.c_float, ctypes.c_float,
                          ctypes.POINTER(ctypes.c_int32)]),
     "vr_tf_release": (S, [P, ctypes.c_int32]),
