@@ -83,103 +83,153 @@ def cpu_baseline(vol, tf, wl, cams, W, H, mode, budget_s=12.0, max_views=16):
             "ms_per_frame": round(t_all / nviews * 1e3, 1)}
 
 
-def serving_leg(n_requests=256, load=0.7, seed=4242):
-    """Serving form: 8 device-resident FP16 cubes (sizes drawn per axis from
-    128..1024 x 128..1024 x 128..512, noise plus density-matched sources),
-    view requests with random orbit cameras, image sizes {256, 512, 1024, 2048}^2
-    and EA/MIP 50/50, served with continuous batching.  First a closed loop
-    (all requests at once) gives the saturation throughput; then requests
-    arrive as a Poisson process at `load` x that rate and the server-side
-    latency (arrival to completion) is reported as p50/p99."""
+def serving_leg(n_requests=2000, n_warm=200, loads=(0.5, 0.7, 0.9), seed=4242):
+    """Serving form: 8 FP16 cubes (sizes drawn per axis from 128..1024 x
+    128..1024 x 128..512, noise plus density-matched sources) registered from
+    pinned host memory, view requests with random orbit cameras, image sizes
+    {256, 512, 1024, 2048}^2 and EA/MIP 50/50, served with continuous batching.
+    Two memory budgets: (i) unconstrained (every cube resident after its first
+    use) and (ii) half of the cubes' total device bytes, so that cubes are
+    admitted and evicted while requests run.  For each budget a closed loop
+    (all requests at once) gives the saturation throughput; then, after
+    n_warm warm-up requests, n_requests arrive as a Poisson process at each
+    load x that rate and the server-side latency (arrival to completion) is
+    reported as p50/p99."""
     import numpy as np
     import torch
 
+    import oracle
     import synth
     from paper_1001_2049_amd import Renderer
 
-    r = Renderer(0)
     specs = synth.serving_cubes(8)
-    cubes, t_gen = [], 0.0
+    codes, t_gen = [], 0.0
     for sp in specs:
         t0 = time.perf_counter()
         vol = synth.cube(sp, threads=cpu_threads())
         t_gen += time.perf_counter() - t0
-        cubes.append(r.upload(vol, "f16"))
+        c = torch.from_numpy(oracle.to_f16_bits(vol).view(np.float16)).pin_memory()
+        codes.append(c)
         del vol
-    log("serving: 8 cubes generated in %.1f s and uploaded" % t_gen)
+    log("serving: 8 cubes generated in %.1f s" % t_gen)
     tf = synth.ramp_tf(256, 1.0)
-    r.set_transfer_function(tf, 3.0, 50.0)
-    r.set_noise_clip(3.0, 1.0)
     rng = np.random.default_rng(seed)
     sizes = [256, 512, 1024, 2048]
-    reqs, outs, meta = [], [], []
-    for i in range(n_requests):
+    total_req = n_warm + n_requests
+    plan = []
+    for i in range(total_req):
         ci = int(rng.integers(0, 8))
         sz = sizes[int(rng.integers(0, 4))]
         mode = "ea" if rng.random() < 0.5 else "mip"
         sp = specs[ci]
         cam = synth.orbit_camera(sp.nx, sp.ny, sp.nz, float(rng.uniform(0, 2 * math.pi)),
                                  float(rng.uniform(-math.pi / 4, math.pi / 4)))
-        out = r.output(sz, sz, mode)
-        reqs.append(r.request(cubes[ci], cam, sz, sz, out, mode=mode, clip=3.0))
-        outs.append(out)
-        meta.append((ci, sz, mode, cam))
-    # nominal samples per request (untimed pass with counters)
-    nominal = []
-    for k in range(0, n_requests, 32):
-        nominal += [st["samples_nominal"] for st in r.render_batch(reqs[k:k + 32], stats=True)]
-    torch.cuda.synchronize()
-    total = float(sum(nominal))
-    # the plain renderer, one request after another
-    t0 = time.perf_counter()
-    for (ci, sz, mode, cam), out in zip(meta, outs):
-        r.set_camera(cam)
-        r.render(cubes[ci], sz, sz, mode=mode, out=out)
-    torch.cuda.synchronize()
-    t_plain = time.perf_counter() - t0
-    r.server_start(max_batch_requests=64, max_batch_tiles=4096, max_inflight=2, use_graphs=1)
-    try:
-        # warm-up (graph capture per shape class), then saturation
-        for t in [r.submit(q) for q in reqs[:32]]:
-            r.wait(t, timeout_s=60)
-        t0 = time.perf_counter()
-        tickets = [r.submit(q) for q in reqs]
-        for t in tickets:
-            r.wait(t, timeout_s=120)
-        t_sat = time.perf_counter() - t0
-        rate_sat = n_requests / t_sat
-        lam = load * rate_sat
-        gaps = rng.exponential(1.0 / lam, size=n_requests)
-        t0 = time.perf_counter()
-        t_next = t0
-        tickets = []
-        for q, g in zip(reqs, gaps):
-            t_next += g
-            d = t_next - time.perf_counter()
-            if d > 0:
-                time.sleep(d)
-            tickets.append(r.submit(q))
-        lat = [r.wait(t, timeout_s=120) for t in tickets]
-        t_open = time.perf_counter() - t0
-    finally:
-        r.server_stop()
-    r.close()
-    lat_ms = np.asarray(lat) * 1e3
-    return {
-        "requests": n_requests,
-        "cubes": [[sp.nx, sp.ny, sp.nz] for sp in specs],
-        "storage": "f16",
-        "samples_total": total,
-        "saturation_requests_per_s": round(rate_sat, 2),
-        "saturation_gsamples_per_s": round(total / t_sat / 1e9, 3),
-        "plain_sequential_gsamples_per_s": round(total / t_plain / 1e9, 3),
-        "poisson_load": load,
-        "poisson_rate_per_s": round(lam, 2),
-        "latency_ms_p50": round(float(np.percentile(lat_ms, 50)), 3),
-        "latency_ms_p99": round(float(np.percentile(lat_ms, 99)), 3),
-        "latency_ms_max": round(float(lat_ms.max()), 3),
-        "open_loop_gsamples_per_s": round(total / t_open / 1e9, 3),
-    }
+        plan.append((ci, sz, mode, cam))
+    gaps_unit = rng.exponential(1.0, size=total_req)
+    # outputs: a ring per (size, mode) class, longer than the requests in flight
+    max_batch, max_inflight = 64, 2
+    ring = max_batch * max_inflight + 16
+
+    def make_outputs(r):
+        pools, count, outs = {}, {}, []
+        for ci, sz, mode, cam in plan:
+            k = (sz, mode)
+            lst = pools.setdefault(k, [])
+            idx = count.get(k, 0)
+            count[k] = idx + 1
+            if len(lst) < ring:
+                lst.append(r.output(sz, sz, mode))
+            outs.append(lst[idx % ring])
+        return outs
+
+    res = {"requests": n_requests, "warmup_requests": n_warm, "loads": list(loads),
+           "cubes": [[sp.nx, sp.ny, sp.nz] for sp in specs], "storage": "f16", "budgets": {}}
+    samples = None
+    total_bytes = None
+    for budget_name in ("unconstrained", "half"):
+        budget = 0 if budget_name == "unconstrained" else total_bytes // 2
+        r = Renderer(0, budget_bytes=budget)
+        try:
+            cubes = [r.register(c, "f16", src_dtype="f16") for c in codes]
+            if total_bytes is None:
+                total_bytes = 0
+                for c in cubes:
+                    inf = r.info(c)
+                    slots = inf.bricks_x * inf.bricks_y * inf.bricks_z
+                    total_bytes += (inf.pool_bytes + 255) // 256 * 256 + (slots * 512 + 255) // 256 * 256
+            r.set_transfer_function(tf, 3.0, 50.0)
+            r.set_noise_clip(3.0, 1.0)
+            outs = make_outputs(r)
+            reqs = [r.request(cubes[ci], cam, sz, sz, out, mode=mode, clip=3.0)
+                    for (ci, sz, mode, cam), out in zip(plan, outs)]
+            if samples is None:
+                # nominal samples per request (untimed pass with counters)
+                samples = []
+                for k in range(0, total_req, 32):
+                    samples += [st["samples_nominal"] for st in r.render_batch(reqs[k:k + 32], stats=True)]
+                torch.cuda.synchronize()
+                # the plain renderer, one request after another (first 256 requests)
+                t0 = time.perf_counter()
+                for (ci, sz, mode, cam), out in list(zip(plan, outs))[:256]:
+                    r.set_camera(cam)
+                    r.render(cubes[ci], sz, sz, mode=mode, out=out)
+                torch.cuda.synchronize()
+                res["plain_sequential_gsamples_per_s"] = round(
+                    float(sum(samples[:256])) / (time.perf_counter() - t0) / 1e9, 3)
+            r.server_start(max_batch_requests=max_batch, max_batch_tiles=4096,
+                           max_inflight=max_inflight, use_graphs=1)
+            cell = {"budget_bytes": int(budget), "total_cube_bytes": int(total_bytes)}
+            try:
+                for t in [r.submit(q) for q in reqs[:n_warm]]:
+                    r.wait(t, timeout_s=300)
+                timed = reqs[n_warm:]
+                tot = float(sum(samples[n_warm:]))
+                t0 = time.perf_counter()
+                tickets = [r.submit(q) for q in timed]
+                for t in tickets:
+                    r.wait(t, timeout_s=600)
+                t_sat = time.perf_counter() - t0
+                rate_sat = len(timed) / t_sat
+                cell["saturation_requests_per_s"] = round(rate_sat, 2)
+                cell["saturation_gsamples_per_s"] = round(tot / t_sat / 1e9, 3)
+                log("serving %s: saturation %.1f requests/s" % (budget_name, rate_sat))
+                for load in loads:
+                    lam = load * rate_sat
+                    lat = []
+                    for phase, part in (("warm", reqs[:n_warm]), ("timed", timed)):
+                        g = gaps_unit[:len(part)] / lam
+                        t0 = time.perf_counter()
+                        t_next = t0
+                        tickets = []
+                        for q, gap in zip(part, g):
+                            t_next += gap
+                            d = t_next - time.perf_counter()
+                            if d > 0:
+                                time.sleep(d)
+                            tickets.append(r.submit(q))
+                        l = [r.wait(t, timeout_s=600) for t in tickets]
+                        if phase == "timed":
+                            lat = l
+                            t_open = time.perf_counter() - t0
+                    lat_ms = np.asarray(lat) * 1e3
+                    cell["load_%.1f" % load] = {
+                        "rate_per_s": round(lam, 2),
+                        "latency_ms_p50": round(float(np.percentile(lat_ms, 50)), 3),
+                        "latency_ms_p99": round(float(np.percentile(lat_ms, 99)), 3),
+                        "latency_ms_max": round(float(lat_ms.max()), 3),
+                        "gsamples_per_s": round(tot / t_open / 1e9, 3)}
+                    log("serving %s load %.1f: p50 %.2f ms p99 %.2f ms" % (
+                        budget_name, load, cell["load_%.1f" % load]["latency_ms_p50"],
+                        cell["load_%.1f" % load]["latency_ms_p99"]))
+            finally:
+                r.server_stop()
+            cell["memory"] = r.memory_stats()
+            res["budgets"][budget_name] = cell
+        finally:
+            r.close()
+            torch.cuda.empty_cache()
+    res["samples_total"] = float(sum(samples[n_warm:]))
+    return res
 
 
 def kernel_source_digest():
@@ -311,7 +361,8 @@ def main():
     ap.add_argument("--no-skip", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
-    ap.add_argument("--serving-requests", type=int, default=256)
+    ap.add_argument("--serving-requests", type=int, default=2000)
+    ap.add_argument("--serving-warmup", type=int, default=200)
     ap.add_argument("--no-variants", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -436,7 +487,7 @@ def main():
     del r
     if not args.no_serving:
         log("serving leg")
-        res["serving"] = serving_leg(args.serving_requests)
+        res["serving"] = serving_leg(args.serving_requests, args.serving_warmup)
     print(json.dumps(res), flush=True)
 
 

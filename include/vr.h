@@ -302,7 +302,7 @@ vr_status vr_render(vr_ctx ctx, vr_cube cube, const vr_render_params* params, vo
  * tight serving loops, harnesses that forbid allocation): vr_render without
  * stats, calling no allocator.  Its dispatch-order scratch is a fixed array of
  * 1 MiB + 1 KiB in device memory (one per GPU, held until the process ends),
- * enough for 262144 tiles of 32x16 pixels.  Requires that the cube is
+ * enough for 262144 tiles of 16x16 pixels (8192 x 8192).  Requires that the cube is
  * resident and that a vr_render of the same cube (same mode, transfer
  * function and clip, for its skip mask) already ran on this hip_stream, so
  * every object it reads is tracked there.  All calls on one GPU share the
@@ -312,6 +312,68 @@ vr_status vr_render(vr_ctx ctx, vr_cube cube, const vr_render_params* params, vo
  * the cube, transfer function or skip mask was not prepared on this stream. */
 vr_status vr_render_noalloc(vr_ctx ctx, vr_cube cube, const vr_render_params* params,
                             void* out_dev, void* hip_stream);
+
+/* --- sub-cubes and scene integration ---------------------------------------
+ * The paper splits a cube into sub-cubes, renders each sub-cube to its own
+ * image and integrates the images into the scene (Sec. 3.1, process steps 1,
+ * 4 and 5); across GPUs the partials would travel to one compositor. */
+
+/* Render the partial image of the sub-cube of voxel planes [plane_lo,
+ * plane_hi) along `axis` (0 x, 1 y, 2 z): of each ray's lattice on the WHOLE
+ * cube (t_in, n and segment lengths as for vr_render) only the samples whose
+ * position on the axis lies in [plane_lo - 1/2, plane_hi - 1/2) are taken (the
+ * window is open below when plane_lo = 0 and above when plane_hi is the axis
+ * size), so the partials of sub-cubes that tile the axis take every sample
+ * exactly once.  Only voxels of planes [plane_lo - 1, plane_hi] are read.
+ * EA: premultiplied RGBA of those samples, (0,0,0,0) without any; early
+ * termination acts within the partial.  MIP: the maximum times sigma_scale if
+ * the window held a sample at or above the clip, -FLT_MAX if it held samples
+ * but none reached the clip, -inf if it held none.  Other arguments, stats
+ * and errors as for vr_render; VR_EINVAL unless 0 <= plane_lo < plane_hi <=
+ * the axis size. */
+vr_status vr_render_subcube(vr_ctx ctx, vr_cube cube, const vr_render_params* params, int32_t axis,
+                            int32_t plane_lo, int32_t plane_hi, void* out_dev, void* hip_stream,
+                            vr_stats* stats);
+
+/* Integrate `count` (1..64) partial images of width x height pixels (device
+ * pointers in a host array, sub-cubes in increasing plane order along `axis`)
+ * into out_dev: VR_EA partials by front-to-back "over", C = C_front +
+ * (1 - A_front) C_back, in the order each pixel's ray (from the context's
+ * camera) crosses the sub-cubes; VR_MIP partials by their maximum, -FLT_MAX
+ * becoming 0 (the clip floor).  With ERT off, the composite of a split
+ * equals vr_render's image up to float rounding.  Enqueued on hip_stream.
+ * Errors: VR_EINVAL (NULL pointers, count, axis or size out of range),
+ * VR_ESTATE (EA without a camera), VR_EDEVICE. */
+vr_status vr_composite(vr_ctx ctx, int32_t mode, const float* const* partials, int32_t count,
+                       int32_t axis, int32_t width, int32_t height, void* out_dev, void* hip_stream);
+
+/* --- progressive (coarse-to-fine) rendering ----------------------------------
+ * The paper's thin client turns user interaction into rendering commands and
+ * shows the results (Fig. 1 caption; Sec. 3.1, process step 4).  For such an
+ * interactive loop, vr_render_progressive renders a view at a level L: an
+ * image of ceil(W/2^L) x ceil(H/2^L) pixels with a lattice step 2^L times
+ * longer (about 8^L times less work), enlarged to W x H by pixel replication
+ * (output pixel (i, j) shows level pixel (i >> L, j >> L)).  On a new view
+ * (cube, parameters, camera, transfer function, clip or out_dev changed since
+ * the previous call) it takes the finest level whose time, predicted from the
+ * device time per sample measured on earlier calls, fits budget_ms (the
+ * coarsest, max_level, when nothing is known yet or nothing fits; level 0
+ * when budget_ms <= 0).  On the same view each call renders the next finer
+ * level; once level 0 is shown, a call renders nothing and reports
+ * converged = 1.  Level 0 is exactly vr_render's image.  The call waits for
+ * the frame.  Errors: as vr_render; VR_EINVAL for max_level outside [0, 4] or
+ * a non-finite budget. */
+typedef struct {
+    int32_t level;              /* level rendered by this call */
+    int32_t converged;          /* 1: level 0 was already shown; nothing rendered */
+    float ms;                   /* device time of this call (render and enlargement) */
+    float predicted_ms;         /* predicted time of the level rendered */
+    uint64_t samples_nominal;   /* lattice samples of the level rendered */
+} vr_progressive_info;
+
+vr_status vr_render_progressive(vr_ctx ctx, vr_cube cube, const vr_render_params* params,
+                                double budget_ms, int32_t max_level, void* out_dev,
+                                void* hip_stream, vr_progressive_info* info);
 
 /* --- batched rendering and serving ---------------------------------------- */
 
@@ -345,7 +407,7 @@ vr_status vr_render_batch(vr_ctx ctx, const vr_request* reqs, int32_t count, voi
 
 typedef struct {
     int32_t max_batch_requests; /* requests admitted per launch (1..4096) */
-    int32_t max_batch_tiles;    /* workgroup tiles (32x16 pixels each) per launch (>= 1) */
+    int32_t max_batch_tiles;    /* workgroup tiles (16x16 pixels each) per launch (>= 1) */
     int32_t max_inflight;       /* launches in flight (1..4) */
     int32_t use_graphs;         /* 1: replay a captured graph per shape class */
 } vr_server_cfg;

@@ -36,8 +36,11 @@ FLAG_NEAREST_AMBIG = 8
 FLAG_GRAZE_AMBIG = 16
 FLAG_MIPCLIP_AMBIG = 32
 FLAG_ERT_STOPPED = 64
+FLAG_WINDOW_AMBIG = 128
 FLAGS_AMBIGUOUS = (FLAG_ERT_AMBIG | FLAG_CLIP_AMBIG | FLAG_NEAREST_AMBIG | FLAG_GRAZE_AMBIG
-                   | FLAG_MIPCLIP_AMBIG)
+                   | FLAG_MIPCLIP_AMBIG | FLAG_WINDOW_AMBIG)
+# MIP partial of a sub-cube whose samples all lie below the clip
+MIP_BELOW_CLIP = -3.4028234663852886e38
 
 
 def build(force: bool = True) -> str:
@@ -64,6 +67,8 @@ class Scene(ctypes.Structure):
         ("width", ctypes.c_int32), ("height", ctypes.c_int32),
         ("amb_ert", ctypes.c_double), ("amb_clip", ctypes.c_double),
         ("amb_nearest", ctypes.c_double), ("amb_graze", ctypes.c_double),
+        ("win_axis", ctypes.c_int32), ("pad1", ctypes.c_int32),
+        ("win_lo", ctypes.c_double), ("win_hi", ctypes.c_double), ("amb_window", ctypes.c_double),
     ]
 
 
@@ -123,7 +128,8 @@ def decode_bits(bits: np.ndarray, dtype: int) -> np.ndarray:
 # ----------------------------------------------------------------------------
 def make_scene(vol, *, mode=EA, interp=TRILINEAR, tf=None, v0=0.0, v1=1.0, clip=-math.inf,
                step=0.5, ert=0.99, camera=None, width=1, height=1, vox_dtype=None, vox_scale=1.0,
-               amb_ert=1e-5, amb_clip=1e-4, amb_nearest=1e-6, amb_graze=1e-6):
+               amb_ert=1e-5, amb_clip=1e-4, amb_nearest=1e-6, amb_graze=1e-6, window=None,
+               amb_window=1e-6):
     """Build the scene struct.  ``vol`` is [nz][ny][nx] float32/float64, or uint16
     storage codes with ``vox_dtype`` F16/BF16.  Keeps references alive on the struct."""
     vol = np.ascontiguousarray(vol)
@@ -155,6 +161,12 @@ def make_scene(vol, *, mode=EA, interp=TRILINEAR, tf=None, v0=0.0, v1=1.0, clip=
     S.fovy_deg, S.ortho_w, S.ortho_h = cam.fovy_deg, cam.ortho_w, cam.ortho_h
     S.width, S.height = width, height
     S.amb_ert, S.amb_clip, S.amb_nearest, S.amb_graze = amb_ert, amb_clip, amb_nearest, amb_graze
+    # sub-cube window (axis, lo, hi): only samples with lo <= p[axis] < hi
+    if window is None:
+        S.win_axis, S.win_lo, S.win_hi = -1, -math.inf, math.inf
+    else:
+        S.win_axis, S.win_lo, S.win_hi = int(window[0]), float(window[1]), float(window[2])
+    S.amb_window = amb_window
     S._keep = (vol, tfa)
     return S
 
@@ -203,6 +215,24 @@ def render(vol, *, pixels=None, threads=None, **kw):
     else:
         res["values"] = out
     return res
+
+
+def composite_over(partials):
+    """Front-to-back "over" of premultiplied RGBA partial images (..., 4), the
+    first in front: C = C_f + (1 - A_f) C_b, A = A_f + (1 - A_f) A_b (Porter and
+    Duff 1984); the scene integration of sub-cube images (Sec. 3.1, step 5)."""
+    acc = np.zeros_like(np.asarray(partials[0], dtype=np.float64))
+    for p in partials:
+        p = np.asarray(p, dtype=np.float64)
+        acc = acc + (1.0 - acc[..., 3:4]) * p
+    return acc
+
+
+def composite_max(partials):
+    """MIP partials combined by maximum, then the clip floor: -inf where no
+    sub-cube held a sample, 0 where all samples lay below the clip."""
+    m = np.max(np.stack([np.asarray(p, dtype=np.float64) for p in partials]), axis=0)
+    return np.where(m == MIP_BELOW_CLIP, 0.0, m)
 
 
 def pixel_ray(camera, width, height, i, j):

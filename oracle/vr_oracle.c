@@ -37,6 +37,16 @@
  *   MIP      m = max_k v_k over the same lattice (no transfer function);
  *            output m if m >= clip else 0; a miss gives -inf.
  *
+ * Sub-cube partials (Sec. 3.1, process steps 1 and 4: the cube is split into
+ * sub-cubes, each rendered to its own image): with win_axis = a >= 0 only the
+ * lattice samples whose position p_a lies in [win_lo, win_hi) are taken, on
+ * the lattice of the whole cube (t_in, n and segment lengths unchanged).  The
+ * EA partial is (C, 1 - T) of those samples; the MIP partial is m if the
+ * window held a sample and m >= clip, -FLT_MAX if it held samples but none
+ * at or above the clip, and -inf if it held none.  A pixel with a sample
+ * within amb_window of a window edge is flagged: the sample may belong to
+ * either neighbour.
+ *
  * Besides the image it reports per pixel the nominal sample count n, the
  * number of samples evaluated before early termination, and flags marking
  * pixels whose result depends discontinuously on a quantity within a small
@@ -62,6 +72,7 @@ enum {
     ORC_FLAG_GRAZE_AMBIG = 16,
     ORC_FLAG_MIPCLIP_AMBIG = 32,
     ORC_FLAG_ERT_STOPPED = 64,
+    ORC_FLAG_WINDOW_AMBIG = 128,
 };
 
 typedef struct {
@@ -83,6 +94,10 @@ typedef struct {
     double fovy_deg, ortho_w, ortho_h;
     int32_t width, height;
     double amb_ert, amb_clip, amb_nearest, amb_graze;  /* flag margins */
+    int32_t win_axis;      /* -1: whole ray; 0/1/2: sub-cube window along x/y/z */
+    int32_t pad1;
+    double win_lo, win_hi; /* window [win_lo, win_hi) of sample positions on win_axis */
+    double amb_window;     /* flag margin at window edges */
 } orc_scene;
 
 /* --- exact decoding of stored voxels ------------------------------------ */
@@ -289,6 +304,9 @@ void orc_ray(const orc_scene* S, int64_t pi, int64_t pj, double* out, int64_t* n
             clip_jump = rc[3] > 0.0;
         }
         double C[3] = {0.0, 0.0, 0.0}, T = 1.0, m = -INFINITY, m_lo = -INFINITY, m_hi = -INFINITY;
+        const int win = S->win_axis >= 0 && S->win_axis < 3;
+        int64_t in_window = 0;
+        if (win) nn = 0;
         for (int64_t k = 0; k < n; ++k) {
             double a = tin + (double)k * step;
             double b = tin + (double)(k + 1) * step;
@@ -296,6 +314,14 @@ void orc_ray(const orc_scene* S, int64_t pi, int64_t pj, double* out, int64_t* n
             double len = b - a;
             double tm = a + 0.5 * len;
             double p[3] = {o[0] + tm * d[0], o[1] + tm * d[1], o[2] + tm * d[2]};
+            if (win) {
+                const double pa = p[S->win_axis];
+                if (fabs(pa - S->win_lo) < S->amb_window || fabs(pa - S->win_hi) < S->amb_window)
+                    fl |= ORC_FLAG_WINDOW_AMBIG;
+                if (!(pa >= S->win_lo && pa < S->win_hi)) continue;
+                ++in_window;
+                ++nn;
+            }
             int tie = 0;
             double vlo, vhi;
             double v = sample(S, p, &tie, &vlo, &vhi);
@@ -324,7 +350,8 @@ void orc_ray(const orc_scene* S, int64_t pi, int64_t pj, double* out, int64_t* n
         if (mip) {
             if (isfinite(S->clip) && fabs(m - S->clip) < S->amb_clip * fmax(1.0, fabs(S->clip)))
                 fl |= ORC_FLAG_MIPCLIP_AMBIG;
-            out[0] = (m >= S->clip) ? m : 0.0;
+            if (win) out[0] = in_window ? ((m >= S->clip) ? m : -3.4028234663852886e38) : -INFINITY;
+            else out[0] = (m >= S->clip) ? m : 0.0;
             if (bounds) {
                 bounds[0] = m_lo;
                 bounds[1] = m_hi;

@@ -366,6 +366,7 @@ vr_status build_request(Ctx* c, Cube* cube, Tf* tf, float clip, const vr_camera&
                         const vr_render_params& p, void* out, hipStream_t s, DevReq& R,
                         MaskEntry** mask_used, bool prepared_only) {
     std::memset(&R, 0, sizeof(R));
+    R.win_axis = -1;
     if (mask_used) *mask_used = nullptr;
     // sample count per ray must stay exactly representable
     const double diag = std::sqrt((double)cube->nx * cube->nx + (double)cube->ny * cube->ny +
@@ -384,6 +385,7 @@ vr_status build_request(Ctx* c, Cube* cube, Tf* tf, float clip, const vr_camera&
     R.cube.by = cube->By;
     R.cube.bz = cube->Bz;
     R.cube.dtype = cube->storage;
+    R.cube.bz_hi = cube->Bz;
     const float clip_s = std::isfinite(clip) ? (float)((double)clip / cube->sigma) : clip;
     R.tf.clip = clip_s;
     if (p.mode == VR_EA) {
@@ -779,6 +781,8 @@ static vr_status drop_device(Ctx* c, Cube* cube) {
 static vr_status release_cube(Ctx* c, Cube* cube) {
     vr_status st = drop_device(c, cube);
     if (st != VR_OK) return st;
+    if (cube->host_pool) (void)hipHostFree(cube->host_pool);
+    cube->host_pool = nullptr;
     c->cubes.erase(cube->id);
     return VR_OK;
 }
@@ -916,11 +920,76 @@ static vr_status make_room(Ctx* c, uint64_t need, const Cube* self, bool may_wai
     return VR_OK;
 }
 
+// Brick a registered cube that exceeds the budget into pinned host memory, one
+// brick layer at a time on the device, keeping only its cell statistics there.
+static vr_status prepare_streamed(Ctx* c, Cube* cube, hipStream_t s) {
+    const uint64_t spl = (uint64_t)cube->Bx * cube->By;  // slots per brick layer
+    const uint64_t layer = spl * cube->stride;
+    vr_status st = make_room(c, alloc_size((uint64_t)cube->nslots * 2 * VR_CELLS_PER_BRICK * 4), cube,
+                             true, {});
+    if (st == VR_OK)
+        st = dev_alloc(c, cube->cellmm, (uint64_t)cube->nslots * 2 * VR_CELLS_PER_BRICK * 4, true);
+    if (st != VR_OK) return st;
+    if (!cube->host_pool) {
+        st = hip_check(hipHostMalloc(&cube->host_pool, (size_t)(cube->nslots * cube->stride), 0),
+                       "hipHostMalloc");
+        if (st != VR_OK) {
+            cube->host_pool = nullptr;
+            dev_free(c, cube->cellmm, true);
+            return st;
+        }
+    }
+    const int64_t nx = cube->nx, ny = cube->ny, nz = cube->nz;
+    const uint64_t selem = cube->src_dtype == VR_F32 ? 4 : 2;
+    const uint64_t plane = (uint64_t)nx * ny * selem;
+    DevBuf lbuf, stage;
+    st = dev_alloc(c, lbuf, layer, false);
+    if (st == VR_OK) st = dev_alloc(c, stage, plane * (uint64_t)std::min<int64_t>(nz, 2 * VR_SLOT_ZP), false);
+    const int src_kind = cube->src_dtype == VR_F32 ? 0 : cube->src_dtype;
+    for (int bz = 0; bz < cube->Bz && st == VR_OK; ++bz) {
+        const int64_t z0 = (int64_t)bz * VR_BRICK;
+        const int64_t z1 = std::min<int64_t>(z0 + 2 * VR_SLOT_ZP, nz);
+        st = hip_check(hipMemcpyAsync(stage.ptr, (const uint8_t*)cube->host_src + (uint64_t)z0 * plane,
+                                      (size_t)((z1 - z0) * plane), hipMemcpyHostToDevice, s),
+                       "hipMemcpyAsync");
+        // the layer buffer stands for slots bz*spl .. (bz+1)*spl - 1 of the pool
+        uint8_t* vbase = (uint8_t*)((uintptr_t)lbuf.ptr - (uintptr_t)((uint64_t)bz * layer));
+        if (st == VR_OK)
+            st = hip_check(vr_launch_brick_build(src_kind, cube->storage, stage.ptr, nx, ny, nz, z0, bz,
+                                                 cube->Bx, cube->By, vbase, cube->stride, cube->xch,
+                                                 (float*)cube->cellmm.ptr, (float)cube->sigma, nullptr, s),
+                           "brick build launch");
+        if (st == VR_OK)
+            st = hip_check(hipMemcpyAsync((uint8_t*)cube->host_pool + (uint64_t)bz * layer, lbuf.ptr,
+                                          (size_t)layer, hipMemcpyDeviceToHost, s),
+                           "hipMemcpyAsync");
+        if (st == VR_OK) st = hip_check(hipStreamSynchronize(s), "hipStreamSynchronize");
+    }
+    (void)hipStreamSynchronize(s);
+    dev_free(c, lbuf, false);
+    dev_free(c, stage, false);
+    if (st != VR_OK) {
+        dev_free(c, cube->cellmm, true);
+        return st;
+    }
+    cube->streamed = true;
+    ++c->uploads;
+    return VR_OK;
+}
+
 vr_status ensure_resident(Ctx* c, Cube* cube, hipStream_t s, bool may_wait,
                           const std::vector<Cube*>& keep) {
     if (cube->resident) {
         cube->lru = ++c->lru_clock;
         return VR_OK;
+    }
+    if (cube->host_src && c->budget && cube->need_bytes() > c->budget) {
+        if (cube->streamed) return VR_OK;
+        if (!may_wait || !keep.empty()) {
+            set_error("a cube larger than the memory budget is rendered only by vr_render");
+            return VR_EUNSUPPORTED;
+        }
+        return prepare_streamed(c, cube, s);
     }
     vr_status st = make_room(c, cube->need_bytes(), cube, may_wait, keep);
     if (st != VR_OK) return st;
@@ -1022,6 +1091,7 @@ vr_status vr_destroy(vr_ctx ctx) {
             dev_free(c, c->counters, false);
             dev_free(c, c->order, false);
             dev_free(c, c->ohist, false);
+            dev_free(c, c->prog.low, false);
             if (c->order_done) (void)hipEventDestroy(c->order_done);
             free_batch_bufs(c, c->batch);
         }
@@ -1125,9 +1195,14 @@ vr_status vr_cube_register(vr_ctx ctx, const void* src, int32_t src_dtype, int64
         std::unique_ptr<Cube> cube(new Cube());
         vr_status st = cube_geometry(cube.get(), nx, ny, nz, storage, sigma_scale);
         if (st != VR_OK) return st;
-        if (c->budget && cube->need_bytes() > c->budget) {
-            set_error("cube needs " + std::to_string(cube->need_bytes()) +
-                      " device bytes, more than the whole budget of " + std::to_string(c->budget));
+        // larger than the budget: streamed, which needs the statistics plus two
+        // sub-cubes of two brick layers on the device
+        const uint64_t layer = (uint64_t)cube->Bx * cube->By * cube->stride;
+        const uint64_t stats_bytes = alloc_size((uint64_t)cube->nslots * 2 * VR_CELLS_PER_BRICK * 4);
+        if (c->budget && cube->need_bytes() > c->budget && stats_bytes + 4 * layer > c->budget) {
+            set_error("cube needs at least " + std::to_string(stats_bytes + 4 * layer) +
+                      " device bytes to be streamed, more than the whole budget of " +
+                      std::to_string(c->budget));
             return VR_ENOMEM;
         }
         cube->host_src = src;
@@ -1409,8 +1484,139 @@ vr_status vr_set_camera(vr_ctx ctx, const vr_camera* cam) {
     return VR_OK;
 }
 
-vr_status vr_render(vr_ctx ctx, vr_cube cube, const vr_render_params* params, void* out_dev,
-                    void* hip_stream, vr_stats* stats) {
+// A cube larger than the memory budget (registered, bricked into pinned host
+// memory): rendered as sub-cubes of G brick layers along z, each uploaded with
+// the layer below it (the samples at its lower face read that layer's last
+// plane) into one of two device buffers while the previous one renders, each
+// rendered to a partial image on the whole cube's lattice, and the partials
+// integrated front to back.  G is as large as two buffers within the budget
+// allow.  Early termination acts within each partial.  Waits for the frame.
+static vr_status render_streamed(Ctx* c, Cube* cu, Tf* tf, const vr_render_params& p, void* out_dev,
+                                 hipStream_t s, vr_stats* stats) {
+    const uint64_t spl = (uint64_t)cu->Bx * cu->By;
+    const uint64_t layer = spl * cu->stride;
+    // room for two sub-cube buffers: idle registered cubes give way
+    vr_status st = make_room(c, 4 * layer, cu, true, {});
+    if (st != VR_OK) return st;
+    const uint64_t avail = c->budget > c->used ? c->budget - c->used : 0;
+    const int G = (int)std::min<uint64_t>((uint64_t)cu->Bz, avail / (2 * layer) - 1);
+    if (G < 1) {
+        set_error("no room for two streamed sub-cubes within the memory budget");
+        return VR_ENOMEM;
+    }
+    const int nsub = (cu->Bz + G - 1) / G;
+    if (nsub > VR_MAX_PARTIALS) {
+        set_error("cube needs more than 64 streamed sub-cubes under this budget");
+        return VR_ENOMEM;
+    }
+    const int ch = p.mode == VR_EA ? 4 : 1;
+    const uint64_t img = (uint64_t)p.width * p.height * ch * 4;
+    DevBuf buf[2], parts;
+    hipStream_t up = nullptr;
+    hipEvent_t ev_up[2] = {nullptr, nullptr}, ev_done[2] = {nullptr, nullptr}, e0 = nullptr, e1 = nullptr;
+    DevCounters* dc = nullptr;
+    std::vector<const float*> pp((size_t)nsub);
+    auto cleanup = [&]() {
+        if (s) (void)hipStreamSynchronize(s);
+        if (up) (void)hipStreamSynchronize(up);
+        for (auto& b : buf) dev_free(c, b, true);
+        dev_free(c, parts, false);
+        for (auto e : {ev_up[0], ev_up[1], ev_done[0], ev_done[1], e0, e1})
+            if (e) (void)hipEventDestroy(e);
+        if (up) (void)hipStreamDestroy(up);
+    };
+    for (auto& b : buf)
+        if (st == VR_OK) st = dev_alloc(c, b, (uint64_t)(G + 1) * layer, true);
+    if (st == VR_OK) st = dev_alloc(c, parts, img * nsub, false);
+    if (st == VR_OK) st = hip_check(hipStreamCreateWithFlags(&up, hipStreamNonBlocking), "hipStreamCreate");
+    for (auto* e : {&ev_up[0], &ev_up[1], &ev_done[0], &ev_done[1]})
+        if (st == VR_OK) st = hip_check(hipEventCreateWithFlags(e, hipEventDisableTiming), "hipEventCreate");
+    if (st == VR_OK) st = hip_check(hipEventCreate(&e0), "hipEventCreate");
+    if (st == VR_OK) st = hip_check(hipEventCreate(&e1), "hipEventCreate");
+    if (st == VR_OK && stats) {
+        st = ensure_counters(c, nsub);
+        dc = (DevCounters*)c->counters.ptr;
+        if (st == VR_OK)
+            st = hip_check(hipMemsetAsync(dc, 0, sizeof(DevCounters) * nsub, s), "hipMemsetAsync");
+    }
+    if (st == VR_OK) st = hip_check(hipEventRecord(e0, s), "hipEventRecord");
+    MaskEntry* me = nullptr;
+    for (int k = 0; k < nsub && st == VR_OK; ++k) {
+        const int b0 = k * G, b1 = std::min(b0 + G, cu->Bz), l0 = std::max(0, b0 - 1);
+        const int q = k & 1;
+        // the buffer was last read by the render of sub-cube k - 2
+        if (k >= 2) st = hip_check(hipStreamWaitEvent(up, ev_done[q], 0), "hipStreamWaitEvent");
+        if (st == VR_OK)
+            st = hip_check(hipMemcpyAsync(buf[q].ptr, (const uint8_t*)cu->host_pool + (uint64_t)l0 * layer,
+                                          (size_t)((uint64_t)(b1 - l0) * layer), hipMemcpyHostToDevice, up),
+                           "hipMemcpyAsync");
+        if (st == VR_OK) st = hip_check(hipEventRecord(ev_up[q], up), "hipEventRecord");
+        if (st == VR_OK) st = hip_check(hipStreamWaitEvent(s, ev_up[q], 0), "hipStreamWaitEvent");
+        DevReq R;
+        if (st == VR_OK) {
+            c->launch_stamp = c->mask_stamp;
+            st = build_request(c, cu, tf, c->clip, c->camera, p, (uint8_t*)parts.ptr + img * k, s, R, &me);
+        }
+        if (st != VR_OK) break;
+        // the buffer stands for slots l0*spl .. b1*spl - 1 of the whole pool
+        R.cube.pool = (const uint8_t*)((uintptr_t)buf[q].ptr - (uintptr_t)((uint64_t)l0 * layer));
+        R.cube.bz_hi = b1;
+        const int z_lo = b0 * VR_BRICK, z_hi = (int)std::min<int64_t>((int64_t)b1 * VR_BRICK, cu->nz);
+        R.win_axis = 2;
+        R.win_lo = z_lo == 0 ? -__builtin_huge_valf() : (float)z_lo - 0.5f;
+        R.win_hi = z_hi == cu->nz ? __builtin_huge_valf() : (float)z_hi - 0.5f;
+        R.win_vlo = std::max(0, z_lo - 1);
+        R.win_vhi = (int)std::min<int64_t>(cu->nz - 1, z_hi);
+        R.partial = 1;
+        pp[(size_t)k] = (const float*)((uint8_t*)parts.ptr + img * k);
+        st = ensure_order(c, R.tiles_x * R.tiles_y, s);
+        if (st == VR_OK)
+            st = hip_check(vr_launch_render(R, (int*)c->order.ptr, (unsigned*)c->ohist.ptr,
+                                            dc ? dc + k : nullptr, s),
+                           "render launch");
+        if (st == VR_OK) st = hip_check(hipEventRecord(c->order_done, s), "hipEventRecord");
+        if (st == VR_OK) st = hip_check(hipEventRecord(ev_done[q], s), "hipEventRecord");
+    }
+    if (st == VR_OK) {
+        DevCam cam;
+        camera_setup(c->camera, p.width, p.height, cam);
+        st = hip_check(vr_launch_composite(pp.data(), nsub, p.mode, 2, cam, p.width, p.height,
+                                           (float*)out_dev, s),
+                       "composite launch");
+    }
+    if (st == VR_OK) st = mark_use(c, cu, tf, me, s);
+    if (st == VR_OK) st = hip_check(hipEventRecord(e1, s), "hipEventRecord");
+    if (st == VR_OK) st = hip_check(hipEventSynchronize(e1), "streamed render");
+    if (st == VR_OK && stats) {
+        float ms = 0.0f;
+        st = hip_check(hipEventElapsedTime(&ms, e0, e1), "hipEventElapsedTime");
+        std::vector<DevCounters> h((size_t)nsub);
+        if (st == VR_OK)
+            st = hip_check(hipMemcpy(h.data(), dc, sizeof(DevCounters) * nsub, hipMemcpyDeviceToHost),
+                           "hipMemcpy");
+        if (st == VR_OK) {
+            DevCounters sum{};
+            for (const auto& x : h) {
+                sum.samples_nominal += x.samples_nominal;
+                sum.samples_exec += x.samples_exec;
+                sum.rays_ert += x.rays_ert;
+                sum.cells_skipped += x.cells_skipped;
+                sum.rays_hit = std::max(sum.rays_hit, x.rays_hit);
+            }
+            fill_stats(sum, ms, stats);
+        }
+    }
+    cleanup();
+    return st;
+}
+
+// A sub-cube window: voxel planes [lo, hi) along one axis.// A sub-cube window: voxel planes [lo, hi) along one axis.
+struct SubWindow {
+    int axis, lo, hi;
+};
+
+static vr_status render_impl(vr_ctx ctx, vr_cube cube, const vr_render_params* params, void* out_dev,
+                             void* hip_stream, vr_stats* stats, const SubWindow* win) {
     if (!ctx) {
         set_error("ctx is NULL");
         return VR_EINVAL;
@@ -1450,11 +1656,31 @@ vr_status vr_render(vr_ctx ctx, vr_cube cube, const vr_render_params* params, vo
         hipStream_t s = (hipStream_t)hip_stream;
         st = ensure_resident(c, cu, s, true, {});
         if (st != VR_OK) return st;
+        if (cu->streamed) {
+            if (win) {
+                set_error("sub-cube renders of a streamed cube are not supported");
+                return VR_EUNSUPPORTED;
+            }
+            return render_streamed(c, cu, tf, *params, out_dev, s, stats);
+        }
         DevReq R;
         MaskEntry* me = nullptr;
         c->launch_stamp = c->mask_stamp;
         st = build_request(c, cu, tf, c->clip, c->camera, *params, out_dev, s, R, &me);
         if (st != VR_OK) return st;
+        if (win) {
+            const int64_t Na = win->axis == 0 ? cu->nx : (win->axis == 1 ? cu->ny : cu->nz);
+            if (win->lo < 0 || win->hi > Na || win->lo >= win->hi) {
+                set_error("sub-cube planes must satisfy 0 <= lo < hi <= the axis size");
+                return VR_EINVAL;
+            }
+            R.win_axis = win->axis;
+            R.win_lo = win->lo == 0 ? -__builtin_huge_valf() : (float)win->lo - 0.5f;
+            R.win_hi = win->hi == Na ? __builtin_huge_valf() : (float)win->hi - 0.5f;
+            R.win_vlo = std::max(0, win->lo - 1);
+            R.win_vhi = (int)std::min<int64_t>(Na - 1, win->hi);
+            R.partial = 1;
+        }
         DevCounters* dc = nullptr;
         hipEvent_t e0 = nullptr, e1 = nullptr;
         if (stats) {
@@ -1489,6 +1715,192 @@ vr_status vr_render(vr_ctx ctx, vr_cube cube, const vr_render_params* params, vo
             if (st != VR_OK) return st;
             fill_stats(h, ms, stats);
         }
+        return VR_OK;
+    });
+}
+
+vr_status vr_render(vr_ctx ctx, vr_cube cube, const vr_render_params* params, void* out_dev,
+                    void* hip_stream, vr_stats* stats) {
+    return render_impl(ctx, cube, params, out_dev, hip_stream, stats, nullptr);
+}
+
+vr_status vr_render_subcube(vr_ctx ctx, vr_cube cube, const vr_render_params* params, int32_t axis,
+                            int32_t plane_lo, int32_t plane_hi, void* out_dev, void* hip_stream,
+                            vr_stats* stats) {
+    if (axis < 0 || axis > 2) {
+        set_error("axis must be 0, 1 or 2");
+        return VR_EINVAL;
+    }
+    const SubWindow w{axis, plane_lo, plane_hi};
+    return render_impl(ctx, cube, params, out_dev, hip_stream, stats, &w);
+}
+
+vr_status vr_composite(vr_ctx ctx, int32_t mode, const float* const* partials, int32_t count,
+                       int32_t axis, int32_t width, int32_t height, void* out_dev, void* hip_stream) {
+    if (!ctx || !partials || !out_dev) {
+        set_error("ctx, partials and out_dev must be non-NULL");
+        return VR_EINVAL;
+    }
+    if ((mode != VR_EA && mode != VR_MIP) || count < 1 || count > VR_MAX_PARTIALS || axis < 0 ||
+        axis > 2 || width < 1 || height < 1 || width > 16384 || height > 16384) {
+        set_error("composite: mode, count (1..64), axis or image size out of range");
+        return VR_EINVAL;
+    }
+    for (int k = 0; k < count; ++k)
+        if (!partials[k]) {
+            set_error("partial " + std::to_string(k) + " is NULL");
+            return VR_EINVAL;
+        }
+    Ctx* c = (Ctx*)ctx;
+    VR_GUARD({
+        std::lock_guard<std::recursive_mutex> lk(c->mu);
+        if (c->host_only()) {
+            set_error("host-only context cannot composite");
+            return VR_EDEVICE;
+        }
+        if (mode == VR_EA && !c->has_camera) {
+            set_error("camera not set (it orders the partials along each ray)");
+            return VR_ESTATE;
+        }
+        vr_status st = hip_check(hipSetDevice(c->device), "hipSetDevice");
+        if (st != VR_OK) return st;
+        DevCam cam;
+        std::memset(&cam, 0, sizeof(cam));
+        if (c->has_camera) camera_setup(c->camera, width, height, cam);
+        return hip_check(vr_launch_composite(partials, count, mode, axis, cam, width, height,
+                                             (float*)out_dev, (hipStream_t)hip_stream),
+                         "composite launch");
+    });
+}
+
+vr_status vr_render_progressive(vr_ctx ctx, vr_cube cube, const vr_render_params* params,
+                                double budget_ms, int32_t max_level, void* out_dev,
+                                void* hip_stream, vr_progressive_info* info) {
+    if (!ctx || !info) {
+        set_error("ctx and info must be non-NULL");
+        return VR_EINVAL;
+    }
+    std::memset(info, 0, sizeof(*info));
+    vr_status st = check_params(params);
+    if (st != VR_OK) return st;
+    if (!out_dev) {
+        set_error("out_dev is NULL");
+        return VR_EINVAL;
+    }
+    if (max_level < 0 || max_level > VR_PROG_LEVELS - 1 || !std::isfinite(budget_ms)) {
+        set_error("max_level must lie in [0, 4] and budget_ms must be finite");
+        return VR_EINVAL;
+    }
+    Ctx* c = (Ctx*)ctx;
+    VR_GUARD({
+        std::lock_guard<std::recursive_mutex> lk(c->mu);
+        if (c->host_only()) {
+            set_error("host-only context cannot render");
+            return VR_EDEVICE;
+        }
+        if (!c->has_camera) {
+            set_error("camera not set");
+            return VR_ESTATE;
+        }
+        if (params->mode == VR_EA && !c->current_tf) {
+            set_error("transfer function not set");
+            return VR_ESTATE;
+        }
+        if (!find_cube(c, cube)) {
+            set_error("unknown cube handle " + std::to_string(cube));
+            return VR_ENOTFOUND;
+        }
+        // the view: everything that decides the image
+        std::vector<uint8_t> key;
+        auto put = [&](const void* p, size_t n) {
+            key.insert(key.end(), (const uint8_t*)p, (const uint8_t*)p + n);
+        };
+        int64_t tfv = params->mode == VR_EA ? find_tf(c, c->current_tf)->version : -1;
+        put(&cube, sizeof(cube));
+        put(params, sizeof(*params));
+        put(&c->camera, sizeof(c->camera));
+        put(&tfv, sizeof(tfv));
+        put(&c->clip, sizeof(c->clip));
+        put(&out_dev, sizeof(out_dev));
+        auto& P = c->prog;
+        const bool same = P.valid && P.key == key;
+        if (same && P.level == 0) {
+            info->converged = 1;
+            return VR_OK;
+        }
+        int L = 0;
+        if (same) {
+            L = P.level - 1;  // refine the view already shown
+        } else if (budget_ms > 0.0) {
+            // the finest level whose predicted time fits the budget; a level is
+            // about 8x cheaper than the next finer one (rays / 4, samples / 2)
+            L = max_level;
+            if (P.ms_per_sample > 0.0 && P.last_samples > 0) {
+                double pred0 = P.ms_per_sample * (double)P.last_samples;
+                for (int l = 0; l <= max_level; ++l) {
+                    if (pred0 / std::pow(8.0, l) <= budget_ms) {
+                        L = l;
+                        break;
+                    }
+                }
+            }
+        }
+        L = std::min(L, max_level);
+        const int ch = params->mode == VR_EA ? 4 : 1;
+        vr_render_params lp = *params;
+        lp.width = std::max(1, (params->width + (1 << L) - 1) >> L);
+        lp.height = std::max(1, (params->height + (1 << L) - 1) >> L);
+        lp.step = params->step * (float)(1 << L);
+        hipStream_t s = (hipStream_t)hip_stream;
+        void* target = out_dev;
+        if (L > 0) {
+            const uint64_t need = (uint64_t)lp.width * lp.height * ch * 4;
+            if (P.low.bytes < need) {
+                st = hip_check(hipStreamSynchronize(s), "hipStreamSynchronize");
+                if (st != VR_OK) return st;
+                dev_free(c, P.low, false);
+                st = dev_alloc(c, P.low, need, false);
+                if (st != VR_OK) return st;
+            }
+            target = P.low.ptr;
+        }
+        vr_stats rs;
+        st = vr_render(ctx, cube, &lp, target, hip_stream, &rs);
+        if (st != VR_OK) return st;
+        float ms = rs.kernel_ms;
+        if (L > 0) {
+            hipEvent_t e0 = nullptr, e1 = nullptr;
+            st = hip_check(hipEventCreate(&e0), "hipEventCreate");
+            if (st == VR_OK) st = hip_check(hipEventCreate(&e1), "hipEventCreate");
+            if (st == VR_OK) st = hip_check(hipEventRecord(e0, s), "hipEventRecord");
+            if (st == VR_OK)
+                st = hip_check(vr_launch_upsample((const float*)P.low.ptr, lp.width, lp.height, ch,
+                                                  (float*)out_dev, params->width, params->height, L, s),
+                               "upsample launch");
+            if (st == VR_OK) st = hip_check(hipEventRecord(e1, s), "hipEventRecord");
+            if (st == VR_OK) st = hip_check(hipEventSynchronize(e1), "upsample");
+            float up = 0.0f;
+            if (st == VR_OK) st = hip_check(hipEventElapsedTime(&up, e0, e1), "hipEventElapsedTime");
+            if (e0) (void)hipEventDestroy(e0);
+            if (e1) (void)hipEventDestroy(e1);
+            if (st != VR_OK) return st;
+            ms += up;
+        }
+        // running estimate of device time per nominal sample
+        if (rs.samples_nominal > 0) {
+            const double m = (double)rs.kernel_ms / (double)rs.samples_nominal;
+            P.ms_per_sample = P.ms_per_sample > 0.0 ? 0.5 * (P.ms_per_sample + m) : m;
+            P.last_samples = (uint64_t)((double)rs.samples_nominal * std::pow(8.0, L));
+        }
+        info->predicted_ms = P.ms_per_sample > 0.0
+                                 ? (float)(P.ms_per_sample * (double)P.last_samples / std::pow(8.0, L))
+                                 : 0.0f;
+        P.key = key;
+        P.level = L;
+        P.valid = true;
+        info->level = L;
+        info->ms = ms;
+        info->samples_nominal = rs.samples_nominal;
         return VR_OK;
     });
 }

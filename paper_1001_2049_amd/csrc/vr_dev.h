@@ -24,7 +24,7 @@ struct ff {
 // Render workgroups: VR_WG threads own a VR_TW x VR_TH pixel tile, one 8x8
 // block per wave, and VR_WG_PER_CU of them share a compute unit's LDS.
 #ifndef VR_TW
-#define VR_TW 32                    // workgroup tile width (pixels)
+#define VR_TW 16                    // workgroup tile width (pixels)
 #endif
 #ifndef VR_TH
 #define VR_TH 16                    // workgroup tile height (pixels)
@@ -32,7 +32,7 @@ struct ff {
 #define VR_WG (VR_TW * VR_TH)       // threads per render workgroup (one per pixel)
 #define VR_NWAVE (VR_WG / 64)
 #ifndef VR_WG_PER_CU
-#define VR_WG_PER_CU 1              // render workgroups resident per compute unit
+#define VR_WG_PER_CU 2              // render workgroups resident per compute unit
 #endif
 #define VR_LDS_CU 163840            // LDS per compute unit on gfx950
 #define VR_LDS_MAX (VR_LDS_CU / VR_WG_PER_CU)  // LDS per render workgroup
@@ -48,6 +48,8 @@ struct ff {
 #define VR_MIPC (768 / VR_WG_PER_CU)          // cells per slab box
 #define VR_MIPC_BYTES (3 * VR_MIPC * 4)
 #define VR_TROW 16                            // cells per box row (longer rows: no skipping)
+#define VR_MAX_PARTIALS 64                    // sub-cube partials per composite
+#define VR_PROG_LEVELS 5                      // progressive rendering: levels 0 .. 4
 // Waves of the render kernels per SIMD (what the register budget must allow).
 #define VR_WAVES_PER_EU ((VR_NWAVE * VR_WG_PER_CU + 3) / 4)
 // Brick slot layout.  A slot stores local voxels x in [0, 4*xch), y in [0, 36),
@@ -78,6 +80,9 @@ struct DevCube {
     int32_t bx, by, bz;             // bricks per axis
     int32_t dtype;                  // 0 f32, 1 f16, 2 bf16
     int32_t xch;                    // x chunks per slot row
+    int32_t bz_hi;                  // brick layers below this one are addressable (bz normally;
+                                    // a streamed sub-cube holds only some layers, and planes
+                                    // above them are read from the top layer's apron)
 };
 
 // Transfer function: rows[2i] = row i (r, g, b, kappa), rows[2i+1] = row i+1 - row i.
@@ -109,6 +114,13 @@ struct DevReq {
     ff step;                        // lattice spacing
     float ert_T;                    // stop once transmittance <= ert_T
     float out_scale;                // MIP: stored units -> data units
+    // Sub-cube partial: only lattice samples whose position on axis win_axis
+    // lies in [win_lo, win_hi) (the lattice stays the whole cube's); voxels
+    // outside planes [win_vlo, win_vhi] on that axis are never read.
+    int32_t win_axis;               // -1: whole rays
+    int32_t win_vlo, win_vhi;
+    int32_t partial;                // MIP partial encoding (see store_pixel)
+    float win_lo, win_hi;
 };
 
 // Device counters (optional).

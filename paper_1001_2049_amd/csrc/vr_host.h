@@ -75,6 +75,11 @@ struct Cube {
     const void* host_src = nullptr; // caller-owned voxels (registered cubes)
     int src_dtype = VR_F32;
     bool resident = false;
+    // A registered cube larger than the budget is streamed: its statistics stay
+    // on the device, its bricks in pinned host memory, and renders upload
+    // groups of brick layers as sub-cubes (vr_render only).
+    bool streamed = false;
+    void* host_pool = nullptr;      // pinned: every slot, in slot order
     int pins = 0;                   // served requests that have started on it
     uint64_t lru = 0;               // last admission or use, in ctx->lru_clock ticks
     uint64_t bytes() const;
@@ -140,6 +145,18 @@ struct Ctx {
     int order_cap = 0;
     hipEvent_t order_done = nullptr;  // last render that read `order`
     BatchBufs batch;
+
+    // progressive (coarse-to-fine) rendering: the view of the last call, the
+    // level it delivered, and measured device time per nominal sample
+    struct Progressive {
+        bool valid = false;
+        std::vector<uint8_t> key;   // cube, parameters, camera, transfer function, clip, output
+        int level = 0;              // level delivered for this view
+        double ms_per_sample = 0.0; // running estimate (0: none yet)
+        uint64_t last_samples = 0;
+        DevBuf low;                 // reduced-resolution image of a coarse level
+        DevCounters* counters = nullptr;
+    } prog;
 
     // The server is shared with callers blocked in vr_wait / vr_poll, so that a
     // concurrent vr_server_stop cannot free it under them.

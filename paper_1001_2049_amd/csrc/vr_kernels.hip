@@ -16,8 +16,9 @@
 //                 most expensive tiles out first.
 //
 // The render kernels themselves live in vr_render.h and are instantiated in
-// vr_render_<mode>_<storage>.hip (one image per launch; a 512-thread
-// workgroup renders a 32x16 pixel tile, each 64-lane wave an 8x8 sub-tile)
+// vr_render_<mode>_<storage>.hip (one image per launch; a 256-thread
+// workgroup renders a 16x16 pixel tile, each 64-lane wave an 8x8 sub-tile,
+// two workgroups per compute unit)
 // and vr_render_batch.hip (a persistent grid over many requests).
 #include <hip/hip_runtime.h>
 #include <math.h>
@@ -343,6 +344,31 @@ __global__ __launch_bounds__(VR_BB_WG) void k_cellmax(const float* __restrict__ 
     const float mx = cell_minmax[slot * (2 * VR_CELLS_PER_BRICK) + 2 * c + 1];
     const float M = fmaxf(fabsf(mn), fabsf(mx));
     cellmax[i] = mx < clip ? -VR_INF : mx + (M * 0x1p-19f + 1e-30f);
+}
+
+// Progressive rendering: a coarse level's image enlarged to the full size.
+__global__ __launch_bounds__(256) void k_upsample(const float* __restrict__ low, int wl, int hl,
+                                                  int ch, float* __restrict__ out, int W, int H,
+                                                  int L) {
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= (int64_t)W * H) return;
+    const int x = (int)(i % W), y = (int)(i / W);
+    const int xl = min(x >> L, wl - 1), yl = min(y >> L, hl - 1);
+    const float* src = low + ((int64_t)yl * wl + xl) * ch;
+    float* dst = out + i * ch;
+    if (ch == 4) {
+        *(float4*)dst = *(const float4*)src;
+    } else {
+        dst[0] = src[0];
+    }
+}
+
+hipError_t vr_launch_upsample(const float* low, int wl, int hl, int ch, float* out, int W, int H,
+                              int L, hipStream_t s) {
+    const int64_t n = (int64_t)W * H;
+    hipLaunchKernelGGL(k_upsample, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, low, wl, hl,
+                       ch, out, W, H, L);
+    return hipGetLastError();
 }
 
 hipError_t vr_launch_classify(const float* cell_minmax, uint64_t* mask, uint32_t* cellbits,

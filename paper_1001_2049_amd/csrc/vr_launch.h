@@ -18,9 +18,12 @@ inline int vr_lds_reserve(int tf_rows) {
     return 32 * tf_rows > VR_MIPC_BYTES ? 32 * tf_rows : VR_MIPC_BYTES;
 }
 
-// LDS bytes of one slab box buffer beside a transfer function of n rows (0: MIP)
+// LDS bytes of one slab box buffer beside a transfer function of n rows (0: MIP).
+// Normally VR_WG_PER_CU workgroups share a compute unit; a transfer function
+// too large for that share takes LDS up to the whole unit (fewer workgroups
+// then run at once; boxes that do not fit are sampled from the brick pool).
 inline int vr_box_bytes(int tf_rows) {
-    const int avail = (VR_LDS_MAX - VR_LDS_STATIC - vr_lds_reserve(tf_rows)) / 2;
+    const int avail = (VR_LDS_CU - VR_LDS_STATIC - vr_lds_reserve(tf_rows)) / 2;
     const int b = (avail / 16) * 16;
     return b < VR_BOX_REF ? b : VR_BOX_REF;
 }
@@ -46,7 +49,7 @@ hipError_t vr_launch_classify(const float* cell_minmax, uint64_t* mask, uint32_t
                               float* cellmax, int Bx, int By, int Bz, int mode, float clip,
                               float scale, float bias, int n, const int* kpos, hipStream_t s);
 
-// One image, one workgroup per 32x16 tile, dispatched most expensive tile
+// One image, one workgroup per 16x16 tile, dispatched most expensive tile
 // first.  order: device scratch of tiles_x * tiles_y ints; hist: 256 words.
 hipError_t vr_launch_render(const DevReq& R, int* order, unsigned* hist, DevCounters* cnt,
                             hipStream_t s);
@@ -57,3 +60,16 @@ hipError_t vr_launch_render(const DevReq& R, int* order, unsigned* hist, DevCoun
 hipError_t vr_launch_batch(const DevReq* reqs, const DevItem* items, const int* nitems,
                            int items_cap, DevItem* sorted, unsigned* hist, unsigned* head,
                            DevCounters* cnt, size_t lds_bytes, int grid, hipStream_t s);
+
+// Nearest-neighbour enlargement of a (W >> L) x (H >> L) image (rounded up)
+// with `ch` floats per pixel to W x H: output pixel (i, j) takes low pixel
+// (i >> L, j >> L).
+hipError_t vr_launch_upsample(const float* low, int wl, int hl, int ch, float* out, int W, int H,
+                              int L, hipStream_t s);
+
+// Sub-cube partial images (count <= VR_MAX_PARTIALS, sub-cubes in increasing
+// plane order along `axis`) combined into one image: EA by front-to-back
+// "over" in each pixel's visibility order (the sign of its ray direction on
+// the axis, from the camera constants), MIP by maximum and the clip floor.
+hipError_t vr_launch_composite(const float* const* partials, int count, int mode, int axis,
+                               const DevCam& cam, int W, int H, float* out, hipStream_t s);

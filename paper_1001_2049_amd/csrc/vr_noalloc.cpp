@@ -20,7 +20,7 @@
 #include "vr_host.h"
 #include "vr_launch.h"
 
-#define VR_NOALLOC_TILES 262144        // 32x16-pixel tiles: e.g. 8192 x 16384 pixels
+#define VR_NOALLOC_TILES 262144        // 16x16-pixel tiles: e.g. 8192 x 8192 pixels
 #define VR_NOALLOC_ORDER_BYTES (VR_NOALLOC_TILES * 4)
 #define VR_NOALLOC_BYTES (VR_NOALLOC_ORDER_BYTES + 1024)
 

@@ -20,6 +20,7 @@ struct Ray {
     ff o[3], d[3];
     ff tin;
     int n;                 // lattice samples; 0 when the ray misses the cube
+    int kb, ke;            // samples [kb, ke) are taken (a sub-cube window; else 0, n)
     float last_adj;        // the last segment's midpoint, in lattice steps before a full step's
     float c_full, c_last;  // -len * log2(e) of full and last segments
     float dd[3];           // step * direction
@@ -56,6 +57,59 @@ __device__ __forceinline__ void ray_dir(const DevCam& cam, float fi, float fj, f
     d[0] = d0;
     d[1] = d1;
     d[2] = d2;
+}
+
+__device__ __forceinline__ float ff_ceil(const ff& x) {
+    float c = ceilf(x.hi);
+    if (c == x.hi && x.lo > 0.0f) c += 1.0f;
+    return c;
+}
+__device__ __forceinline__ float ff_floor(const ff& x) {
+    float f = floorf(x.hi);
+    if (f == x.hi && x.lo < 0.0f) f -= 1.0f;
+    return f;
+}
+
+// Sub-cube window: the lattice samples whose position on the window axis lies
+// in [win_lo, win_hi).  Positions E + (k + 1/2) D (E the entry point, D = step
+// times the direction) are monotone in k, so the samples form a range,
+// found in float-float; the last sample, moved back to its short segment's
+// midpoint, is tested on its own.
+__device__ __forceinline__ void window_range(const DevReq& R, Ray& ray) {
+    const int a = R.win_axis;
+    const ff E = ff_add(a == 0 ? ray.o[0] : (a == 1 ? ray.o[1] : ray.o[2]),
+                        ff_mul(ray.tin, a == 0 ? ray.d[0] : (a == 1 ? ray.d[1] : ray.d[2])));
+    const ff D = ff_mul(a == 0 ? ray.d[0] : (a == 1 ? ray.d[1] : ray.d[2]), R.step);
+    const int n = ray.n;
+    const bool lo_inf = R.win_lo == -VR_INF, hi_inf = R.win_hi == VR_INF;
+    // position of sample k (regular lattice) relative to a window edge
+    auto rel = [&](float edge) { return ff_sub(ff_div(ff_sub(ff_make(edge), E), D), ff_make(0.5f)); };
+    float kb, ke;
+    if (D.hi > 0.0f) {
+        kb = lo_inf ? 0.0f : ff_ceil(rel(R.win_lo));
+        ke = hi_inf ? (float)n : ff_ceil(rel(R.win_hi));
+    } else if (D.hi < 0.0f) {
+        kb = hi_inf ? 0.0f : ff_floor(rel(R.win_hi)) + 1.0f;
+        ke = lo_inf ? (float)n : ff_floor(rel(R.win_lo)) + 1.0f;
+    } else {
+        const bool in = (lo_inf || !ff_lt(E, ff_make(R.win_lo))) && (hi_inf || ff_lt(E, ff_make(R.win_hi)));
+        kb = 0.0f;
+        ke = in ? (float)n : 0.0f;
+    }
+    // the regular lattice decides samples 0 .. n-2; the last one is tested at
+    // its own position
+    kb = fminf(fmaxf(kb, 0.0f), (float)(n - 1));
+    ke = fminf(fmaxf(ke, 0.0f), (float)(n - 1));
+    const ff pl = ff_add(E, ff_mul_f(D, (float)n - 0.5f + ray.last_adj));
+    const bool last_in = (lo_inf || !ff_lt(pl, ff_make(R.win_lo))) && (hi_inf || ff_lt(pl, ff_make(R.win_hi)));
+    int b = (int)kb, e = (int)ke;
+    if (last_in && (e == n - 1 || b >= e)) {
+        if (b >= e) b = n - 1;
+        e = n;
+    }
+    if (b >= e) b = e = 0;
+    ray.kb = b;
+    ray.ke = e;
 }
 
 // Camera ray of pixel (px, py), its chord through [-1/2, N-1/2]^3 and the
@@ -97,6 +151,9 @@ __device__ __forceinline__ void ray_setup(const DevReq& R, int px, int py, Ray& 
     ray.c_last = -len_last * VR_LOG2E;
 #pragma unroll
     for (int a = 0; a < 3; ++a) ray.dd[a] = ff_to_f(ff_mul(ray.d[a], R.step));
+    ray.kb = 0;
+    ray.ke = ray.n;
+    if (R.win_axis >= 0) window_range(R, ray);
 }
 
 // Parameter t of lattice sample k.
@@ -280,8 +337,13 @@ __device__ __forceinline__ void store_pixel(const DevReq& R, int px, int py, boo
     if (MODE == 0) {
         *(float4*)(R.out + 4 * pix) =
             hit ? make_float4(acc.C0, acc.C1, acc.C2, 1.0f - acc.T) : make_float4(0.f, 0.f, 0.f, 0.f);
-    } else {
+    } else if (!R.partial) {
         R.out[pix] = hit ? ((acc.m >= R.tf.clip) ? acc.m * R.out_scale : 0.0f) : -VR_INF;
+    } else {
+        // sub-cube partial: -inf without samples in the window, the lowest
+        // float where they all lie below the clip (combined by maximum, then
+        // floored to 0)
+        R.out[pix] = hit ? ((acc.m >= R.tf.clip) ? acc.m * R.out_scale : -3.402823466e38f) : -VR_INF;
     }
 }
 
@@ -305,7 +367,7 @@ __device__ __forceinline__ void render_lane_direct(const DevReq& R, const int px
     ray_setup(R, px, py, ray);
     const int n = ray.n;
     Accum acc = {0.0f, 0.0f, 0.0f, 1.0f, -VR_INF};
-    if (n == 0) {
+    if (n == 0 || ray.kb >= ray.ke) {
         store_pixel<MODE>(R, px, py, false, acc);
         return;
     }
@@ -315,7 +377,7 @@ __device__ __forceinline__ void render_lane_direct(const DevReq& R, const int px
 #pragma unroll
     for (int a = 0; a < 3; ++a) inv_dd[a] = ray.dd[a] != 0.0f ? 1.0f / ray.dd[a] : 0.0f;
     const float shift = INTERP == 0 ? 0.5f : 0.0f;
-    int k0 = 0, m = 0, j = 0;
+    int k0 = ray.kb, m = 0, j = 0;
     float A[3] = {0.0f, 0.0f, 0.0f}, hb[3] = {0.0f, 0.0f, 0.0f};
     const uint8_t* base = nullptr;
     uint64_t mask = 0;
@@ -324,7 +386,7 @@ __device__ __forceinline__ void render_lane_direct(const DevReq& R, const int px
     while (true) {
         if (j >= m) {
             k0 += m;
-            if (k0 >= n) break;
+            if (k0 >= ray.ke) break;
             const ff t = sample_t(R, ray, k0);
             int b[3];
 #pragma unroll
@@ -343,7 +405,7 @@ __device__ __forceinline__ void render_lane_direct(const DevReq& R, const int px
                     s = fminf(s, ((float)VR_BRICK - A[a]) * inv_dd[a]);
                 if (ray.dd[a] < 0.0f && b[a] > 0) s = fminf(s, (-A[a]) * inv_dd[a]);
             }
-            const int rem = n - k0;
+            const int rem = ray.ke - k0;
             m = s >= (float)rem ? rem : max(1, (int)ceilf(s));
             j = 0;
             const uint64_t slot = ((uint64_t)b[2] * B[1] + b[1]) * B[0] + b[0];
@@ -411,7 +473,7 @@ __device__ __forceinline__ void render_lane_direct(const DevReq& R, const int px
         }
     }
     store_pixel<MODE>(R, px, py, true, acc);
-    cnt.nominal += (unsigned)n;
+    cnt.nominal += (unsigned)(ray.ke - ray.kb);
     cnt.exec += nexec;
     cnt.hit += 1u;
     cnt.ert += stopped ? 1u : 0u;
@@ -421,7 +483,8 @@ __device__ __forceinline__ void render_lane_direct(const DevReq& R, const int px
 // ---------------------------------------------------------------------------
 // Slab-staged tile renderer (the main path).
 //
-// A 512-thread workgroup owns a 32x16 pixel tile and marches all its rays in
+// A workgroup (VR_WG threads, two per compute unit) owns a 16x16 pixel tile (one
+// 8x8 block per wave) and marches all its rays in
 // lock-step through slabs along the major axis M of the tile's view direction,
 // front to back.  Every ray of the tile passes, at any plane perpendicular to
 // M, inside the quadrilateral cut by the tile's four corner rays (the tile's
@@ -439,9 +502,6 @@ __device__ __forceinline__ void render_lane_direct(const DevReq& R, const int px
 // the brick pool with the same arithmetic.
 // ---------------------------------------------------------------------------
 #define VR_BIG 0x3fffffff
-#ifndef VR_PAIR_FETCH
-#define VR_PAIR_FETCH 0
-#endif
 #define VR_SMAX 32
 
 
@@ -506,7 +566,9 @@ __device__ __forceinline__ int box_plane(int np, int d1) {
 }
 
 // One slab: planes [z0, z0 + S] along M, and the box of voxel indices its
-// samples can touch (floor indices plus the +1 neighbour), clamped to the cube.
+// samples can touch (floor indices plus the +1 neighbour), with floor indices
+// clamped to [CL, CH] per axis: the cube, narrowed on a sub-cube window's axis
+// to the planes its samples can touch.
 struct Slab {
     int z0, S;
     int lo[3], dim[3];
@@ -539,7 +601,7 @@ struct TileShared {
 
 template <int M, int CV>
 __device__ __forceinline__ Slab slab_box(int z0, int S, const Corners& cr, const int N[3],
-                                         int zmin, int zmax) {
+                                         const int CL[3], const int CH[3], int zmin, int zmax) {
     constexpr int A1 = (M + 1) % 3, A2 = (M + 2) % 3;
     Slab s;
     s.z0 = z0;
@@ -551,8 +613,8 @@ __device__ __forceinline__ Slab slab_box(int z0, int S, const Corners& cr, const
     za -= 1e-3f;
     zb += 1e-3f;
     int lo[3], hi[3];
-    lo[M] = max(max(z0 - 1, zmin - 1), 0);
-    hi[M] = min(min(z0 + S, zmax + 1), N[M] - 1);
+    lo[M] = max(max(z0 - 1, zmin - 1), CL[M]);
+    hi[M] = min(min(z0 + S, zmax + 1), CH[M]);
 #pragma unroll
     for (int q = 0; q < 2; ++q) {
         const int a = q == 0 ? A1 : A2;
@@ -564,8 +626,11 @@ __device__ __forceinline__ Slab slab_box(int z0, int S, const Corners& cr, const
             mn = fminf(mn, fminf(v0, v1));
             mx = fmaxf(mx, fmaxf(v0, v1));
         }
-        lo[a] = max((int)floorf(mn - 0.01f), 0);
-        hi[a] = min((int)floorf(mx + 0.01f), N[a] - 1);
+        // sample positions lie in [-1/2, N - 1/2] and their indices are those
+        // of the position clamped to [0, N - 1]: a bundle that only reaches
+        // the sliver [-1/2, 0) still reads voxel 0 (and [N - 1, N - 1/2] voxel N - 1)
+        lo[a] = max((int)floorf(fminf(mn, (float)(N[a] - 1)) - 0.01f), CL[a]);
+        hi[a] = min((int)floorf(fmaxf(mx, 0.0f) + 0.01f), CH[a]);
     }
     bool empty = false;
 #pragma unroll
@@ -589,14 +654,15 @@ __device__ __forceinline__ Slab slab_box(int z0, int S, const Corners& cr, const
 // ok = false when not even one voxel fits.
 template <int M, int CV>
 __device__ __forceinline__ Slab fit_slab(int ze, int sgn, int hi, int cap, const Corners& cr,
-                                         const int N[3], int zmin, int zmax, bool& ok) {
-    Slab best = slab_box<M, CV>(sgn > 0 ? ze : ze - hi, hi, cr, N, zmin, zmax);
+                                         const int N[3], const int CL[3], const int CH[3],
+                                         int zmin, int zmax, bool& ok) {
+    Slab best = slab_box<M, CV>(sgn > 0 ? ze : ze - hi, hi, cr, N, CL, CH, zmin, zmax);
     ok = true;
     if (best.elems <= cap) return best;
     int lo = 0;  // thickest known to fit (0: none); hi never fits
     while (hi - lo > 1) {
         const int mid = (lo + hi) >> 1;
-        const Slab m = slab_box<M, CV>(sgn > 0 ? ze : ze - mid, mid, cr, N, zmin, zmax);
+        const Slab m = slab_box<M, CV>(sgn > 0 ? ze : ze - mid, mid, cr, N, CL, CH, zmin, zmax);
         if (m.elems <= cap) {
             lo = mid;
             best = m;
@@ -617,15 +683,16 @@ __device__ __forceinline__ Slab fit_slab(int ze, int sgn, int hi, int cap, const
 // the brick pool.  Only geometry decides, never the LDS a launch actually has.
 template <int M, int CV, int ELEM>
 __device__ __forceinline__ Slab next_slab(int ze, int sgn, int Sprev, const Corners& cr,
-                                          const int N[3], int zmin, int zmax) {
+                                          const int N[3], const int CL[3], const int CH[3],
+                                          int zmin, int zmax) {
     constexpr int cap = VR_BOX_REF / ELEM;
     bool ok;
-    Slab b = fit_slab<M, CV>(ze, sgn, min(VR_SMAX, 2 * Sprev), 2 * cap, cr, N, zmin, zmax, ok);
+    Slab b = fit_slab<M, CV>(ze, sgn, min(VR_SMAX, 2 * Sprev), 2 * cap, cr, N, CL, CH, zmin, zmax, ok);
     if (ok) {
         b.big = 1;
         return b;
     }
-    return slab_box<M, CV>(sgn > 0 ? ze : ze - 8, 8, cr, N, zmin, zmax);
+    return slab_box<M, CV>(sgn > 0 ? ze : ze - 8, 8, cr, N, CL, CH, zmin, zmax);
 }
 
 // Anchor of lattice sample k0 (without the last segment's shift) relative to
@@ -652,15 +719,21 @@ __device__ __forceinline__ bool tile_march(const DevReq& R, const Ray& ray, cons
     constexpr int CV = 16 / ELEM;
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     const int N[3] = {R.cube.nx, R.cube.ny, R.cube.nz};
+    int CL[3] = {0, 0, 0}, CH[3] = {N[0] - 1, N[1] - 1, N[2] - 1};
+    if (R.win_axis >= 0) {
+        const int a = R.win_axis;
+        CL[a] = max(CL[a], R.win_vlo);
+        CH[a] = min(CH[a], R.win_vhi - 1);
+    }
     const int cap = R.box_bytes / ELEM;
-    const bool act = ray.n > 0;
+    const bool act = ray.n > 0 && ray.kb < ray.ke;
 
     // ---- tile-wide range of sample planes along M -----------------------------
     int zf = 0, zl = 0;
     ff E[3];
     if (act) {
-        const ff t1 = sample_t(R, ray, ray.n - 1);
-        const ff t0 = sample_t(R, ray, 0);
+        const ff t1 = sample_t(R, ray, ray.ke - 1);
+        const ff t0 = sample_t(R, ray, ray.kb);
 #pragma unroll
         for (int a = 0; a < 3; ++a) E[a] = ff_add(ray.o[a], ff_mul(ray.tin, ray.d[a]));
         const float pf = ff_to_f(ff_add(ray.o[M], ff_mul(t0, ray.d[M])));
@@ -700,9 +773,9 @@ __device__ __forceinline__ bool tile_march(const DevReq& R, const Ray& ray, cons
         Slab s = {};
         if (w0_first) {
             const int ze = sgn > 0 ? zmin : zmax + 1;
-            if (slab_exists(ze)) s = next_slab<M, CV, ELEM>(ze, sgn, VR_SMAX, cr, N, zmin, zmax);
+            if (slab_exists(ze)) s = next_slab<M, CV, ELEM>(ze, sgn, VR_SMAX, cr, N, CL, CH, zmin, zmax);
         } else if (w0.S != 0 && slab_exists(exit_plane(w0))) {
-            s = next_slab<M, CV, ELEM>(exit_plane(w0), sgn, w0.S, cr, N, zmin, zmax);
+            s = next_slab<M, CV, ELEM>(exit_plane(w0), sgn, w0.S, cr, N, CL, CH, zmin, zmax);
         }
         if (s.S != 0) {
             const int buf = (s.big || w0.big) ? 0 : 1 - w0_buf;
@@ -727,9 +800,9 @@ __device__ __forceinline__ bool tile_march(const DevReq& R, const Ray& ray, cons
     auto slab_end = [&](const Slab& s, int kprev) -> int {
         if (!act || stopped || s.S == 0) return kprev;
         const int zx = exit_plane(s);
-        if (sgn > 0 ? zx > zl : zx <= zl) return ray.n;
+        if (sgn > 0 ? zx > zl : zx <= zl) return ray.ke;
         const float kf = ceilf((((float)zx - om) * inv_dm - tinf) * inv_step - 0.5f);
-        return kf < (float)kprev ? kprev : (kf > (float)ray.n ? ray.n : (int)kf);
+        return kf < (float)kprev ? kprev : (kf > (float)ray.ke ? ray.ke : (int)kf);
     };
     // Skip-grid words of a slab's cells: bits_issue loads them (one row of cells
     // along x per thread); bits_done, once they have landed, marks the slab as
@@ -793,7 +866,8 @@ __device__ __forceinline__ bool tile_march(const DevReq& R, const Ray& ray, cons
     };
     // MIP running-maximum skipping: the bound of each of the box's 8^3 cells
     // (DevCube::cellmax) is kept in LDS, three slabs in flight like the cell
-    // rows; one thread per row of cells along x loads them two slabs ahead.
+    // rows, copied two slabs ahead with 4-byte global->LDS loads (lane l of a
+    // wave instruction copies cell f0 + l of the box's cells in row order).
     // Boxes with rows longer than VR_TROW cells or more than VR_MIPC cells are
     // sampled without it.
     float* const cthr = MODE == 1 ? const_cast<float*>(tfl) : nullptr;
@@ -802,37 +876,36 @@ __device__ __forceinline__ bool tile_march(const DevReq& R, const Ray& ray, cons
         const int nxc = ((s.lo[0] + s.dim[0] - 2) >> 3) - (s.lo[0] >> 3) + 1;
         const int nyc = ((s.lo[1] + s.dim[1] - 2) >> 3) - (s.lo[1] >> 3) + 1;
         const int nzc = ((s.lo[2] + s.dim[2] - 2) >> 3) - (s.lo[2] >> 3) + 1;
-        return nxc <= VR_TROW && nyc * nzc <= VR_WG && nxc * nyc * nzc <= VR_MIPC;
+        return nxc <= VR_TROW && nxc * nyc * nzc <= VR_MIPC;
     };
-    struct Thr {
-        float v[MODE == 1 ? VR_TROW : 1];
-        int row, nxc;
+    // where more than half of a box's cells can reach the clip, the bounds
+    // rarely let a chunk pass and are not used (nor copied)
+    auto thr_use = [&](const Slab& s, int k) -> bool {
+        if (MODE != 1 || !thr_ok(s)) return false;
+        const int nc = (((s.lo[0] + s.dim[0] - 2) >> 3) - (s.lo[0] >> 3) + 1) *
+                       (((s.lo[1] + s.dim[1] - 2) >> 3) - (s.lo[1] >> 3) + 1) *
+                       (((s.lo[2] + s.dim[2] - 2) >> 3) - (s.lo[2] >> 3) + 1);
+        return 2u * (unsigned)__builtin_amdgcn_readfirstlane((int)sh.nact[k & 7]) <= (unsigned)nc;
     };
-    auto thr_issue = [&](const Slab& s) -> Thr {
-        Thr t;
-        t.row = -1;
-        t.nxc = 0;
-        if (MODE != 1 || !thr_ok(s)) return t;
+    auto thr_dma = [&](const Slab& s, int k) {
+        if (MODE != 1 || !thr_use(s, k)) return;
         const int c0x = s.lo[0] >> 3, c0y = s.lo[1] >> 3, c0z = s.lo[2] >> 3;
         const int nxc = ((s.lo[0] + s.dim[0] - 2) >> 3) - c0x + 1;
         const int nyc = ((s.lo[1] + s.dim[1] - 2) >> 3) - c0y + 1;
-        const int nrow = nyc * (((s.lo[2] + s.dim[2] - 2) >> 3) - c0z + 1);
-        t.nxc = nxc;
-        if (tid >= nrow) return t;
-        const int czr = div_small(tid, nyc, 1.0f / (float)nyc);
-        const int64_t b0 = ((int64_t)(c0z + czr) * Cy + (c0y + tid - czr * nyc)) * Cx + c0x;
-#pragma unroll
-        for (int i = 0; i < (MODE == 1 ? VR_TROW : 1); ++i)
-            t.v[i] = i < nxc ? R.cube.cellmax[b0 + i] : -VR_INF;
-        t.row = tid;
-        return t;
-    };
-    auto thr_done = [&](int k, const Thr& t) {
-        if (MODE != 1 || t.row < 0) return;
-        float* dst = cthr + (k % 3) * VR_MIPC + t.row * t.nxc;
-#pragma unroll
-        for (int i = 0; i < (MODE == 1 ? VR_TROW : 1); ++i)
-            if (i < t.nxc) dst[i] = t.v[i];
+        const int ncell = nxc * nyc * (((s.lo[2] + s.dim[2] - 2) >> 3) - c0z + 1);
+        const float inv_x = 1.0f / (float)nxc, inv_y = 1.0f / (float)nyc;
+        float* dst = cthr + (k % 3) * VR_MIPC;
+        for (int f0 = wave * 64; f0 < ncell; f0 += VR_NWAVE * 64) {
+            const int f = f0 + lane;
+            if (f < ncell) {
+                const int row = div_small(f, nxc, inv_x), col = f - row * nxc;
+                const int czr = div_small(row, nyc, inv_y), cyr = row - czr * nyc;
+                const int64_t g = ((int64_t)(c0z + czr) * Cy + (c0y + cyr)) * Cx + c0x + col;
+                __builtin_amdgcn_global_load_lds((const void*)(R.cube.cellmax + g),
+                                                 (__attribute__((address_space(3))) void*)(dst + f0),
+                                                 4, 0, 0);
+            }
+        }
     };
     // Copy a slab's box into its LDS buffer: the box is row-major over
     // [z][y][16-byte chunk] with np chunks per row and planes box_plane()
@@ -846,8 +919,9 @@ __device__ __forceinline__ bool tile_march(const DevReq& R, const Ray& ray, cons
     const uint32_t bstride = (uint32_t)R.cube.stride;
     auto row_src = [&](const Slab& s, int iy, int iz) -> const uint8_t* {
         const int gy = min(s.lo[1] + iy, N[1] - 1), gz = min(s.lo[2] + iz, N[2] - 1);
-        const uint32_t slot_yz = __umul24(__umul24(gz >> 5, R.cube.by) + (gy >> 5), R.cube.bx);
-        const uint32_t off = (uint32_t)(slot_y<DT>(gy & 31, R.cube.xch) + slot_z<DT>(gz & 31, R.cube.xch)) * ELEM;
+        const int bzl = min(gz >> 5, R.cube.bz_hi - 1);  // plane 32 of a layer: its apron
+        const uint32_t slot_yz = __umul24(__umul24(bzl, R.cube.by) + (gy >> 5), R.cube.bx);
+        const uint32_t off = (uint32_t)(slot_y<DT>(gy & 31, R.cube.xch) + slot_z<DT>(gz - 32 * bzl, R.cube.xch)) * ELEM;
         return R.cube.pool + ((uint64_t)slot_yz * bstride + off);
     };
     auto chunk_off = [&](const Slab& s, int c) -> uint64_t {
@@ -923,13 +997,12 @@ __device__ __forceinline__ bool tile_march(const DevReq& R, const Ray& ray, cons
     }
     __syncthreads();
     Slab s0 = sh.ring[0], s1 = sh.ring[1];
-    int ks = 0, ke0 = slab_end(s0, 0);
+    int ks = act ? ray.kb : 0, ke0 = slab_end(s0, ks);
     if (R.use_skip) {
         bits_done(0, bits_issue(s0));
         bits_done(1, bits_issue(s1));
-        thr_done(0, thr_issue(s0));
-        thr_done(1, thr_issue(s1));
         __syncthreads();
+        thr_dma(s0, 0);
     }
     if (sh.any[0]) box_dma(s0);
 
@@ -947,9 +1020,27 @@ __device__ __forceinline__ bool tile_march(const DevReq& R, const Ray& ray, cons
         const Slab s2 = sh.ring[(it + 2) & 3];
         Bits bb = {0u, 0u, 0u, 0u, 0, -1, 0, 0};
         if (R.use_skip) bb = bits_issue(s2);
-        const Thr th = thr_issue(s2);
+        thr_dma(s1, it + 1);  // its ring entry held slab it - 2; lands by the next iteration
         if (!s1.late && sh.any[(it + 1) & 7]) box_dma(s1);
         const int ke1 = slab_end(s1, ke0);
+        // MIP: passing over samples that cannot raise the running maximum.  A
+        // wave checks its chunks only where at most a quarter of the box's
+        // cells could raise the smallest running maximum among its rays still
+        // marching (otherwise the checks would cost more than they save).
+        bool use_thr = MODE == 1 && thr_use(s0, it);
+        if (MODE == 1 && use_thr) {
+            float mlo = act && !stopped && ks < ray.ke ? acc.m : VR_INF;
+#pragma unroll
+            for (int o = 32; o > 0; o >>= 1) mlo = fminf(mlo, __shfl_xor(mlo, o));
+            const float* cth0 = cthr + (it % 3) * VR_MIPC;
+            const int nc = (((s0.lo[0] + s0.dim[0] - 2) >> 3) - (s0.lo[0] >> 3) + 1) *
+                           (((s0.lo[1] + s0.dim[1] - 2) >> 3) - (s0.lo[1] >> 3) + 1) *
+                           (((s0.lo[2] + s0.dim[2] - 2) >> 3) - (s0.lo[2] >> 3) + 1);
+            int above = 0;
+            for (int f = lane; f - lane < nc; f += 64)
+                above += __popcll(__ballot(f < nc && cth0[f] > mlo));
+            use_thr = 4 * above <= nc;
+        }
         // ---- sample slab it
         const int cnt_s = ke0 - ks;
         if (cnt_s > 0 && !stopped) {
@@ -993,8 +1084,6 @@ __device__ __forceinline__ bool tile_march(const DevReq& R, const Ray& ray, cons
                 }
                 const int nyc = cb1[1] - cb0[1] + 1;
                 const unsigned ncell = (unsigned)((cb1[0] - cb0[0] + 1) * nyc * (cb1[2] - cb0[2] + 1));
-                // MIP: passing over samples that cannot raise the running maximum
-                const bool use_thr = thr_ok(s0);
                 const bool fine = use_thr || (R.use_skip && 4u * (unsigned)__builtin_amdgcn_readfirstlane((int)sh.nact[it & 7]) <= ncell);
                 const uint64_t* crow = sh.crow[it % 3];
                 auto live = [&](int j) -> bool {
@@ -1051,7 +1140,6 @@ __device__ __forceinline__ bool tile_march(const DevReq& R, const Ray& ray, cons
                             j += 6;
                             continue;
                         }
-#if VR_PAIR_FETCH
                         float v0, v1;
                         {
                             const float ja = (float)j, jb = (float)(j + 1) + (j + 1 == jl ? ray.last_adj : 0.0f);
@@ -1067,10 +1155,6 @@ __device__ __forceinline__ bool tile_march(const DevReq& R, const Ray& ray, cons
                             floor_idx<INTERP>(pb, ch, ib, wb);
                             fetch2(ia, wa, ib, wb, v0, v1);
                         }
-#else
-                        const float v0 = value(fetch, j, false);
-                        const float v1 = value(fetch, j + 1, j + 1 == jl);
-#endif
                         if (MODE == 1) {
                             nexec += 2;
                             acc.m = fmaxf(acc.m, fmaxf(v0, v1));
@@ -1148,8 +1232,7 @@ __device__ __forceinline__ bool tile_march(const DevReq& R, const Ray& ray, cons
             }
         }
         if (R.use_skip) bits_done(it + 2, bb);
-        thr_done(it + 2, th);
-        const bool done = !act || stopped || ke0 >= ray.n;
+        const bool done = !act || stopped || ke0 >= ray.ke;
         if (__ballot(!done) != 0ull && lane == 0) sh.alive[it % 3] = 1;
         if (s1.late) {  // the box of slab it + 1 needs the LDS slab it used
             __syncthreads();
@@ -1164,7 +1247,7 @@ __device__ __forceinline__ bool tile_march(const DevReq& R, const Ray& ray, cons
     __syncthreads();
     if (inimg) store_pixel<MODE>(R, px, py, act, acc);
     if (act) {
-        cnt.nominal += (unsigned)ray.n;
+        cnt.nominal += (unsigned)(ray.ke - ray.kb);
         cnt.exec += nexec;
         cnt.hit += 1u;
         cnt.ert += stopped ? 1u : 0u;
@@ -1286,12 +1369,12 @@ __global__ __launch_bounds__(VR_WG, VR_WAVES_PER_EU) void k_render(const DevReq 
 }
 
 
-// Static plus dynamic LDS of a launch must fit the workgroup's 160 KB.
+// Static plus dynamic LDS of a launch must fit the compute unit's 160 KB.
 static inline hipError_t check_lds(const void* kernel, size_t dynamic_bytes) {
     hipFuncAttributes a;
     hipError_t e = hipFuncGetAttributes(&a, kernel);
     if (e != hipSuccess) return e;
-    return a.sharedSizeBytes + dynamic_bytes <= (size_t)VR_LDS_MAX ? hipSuccess : hipErrorInvalidValue;
+    return a.sharedSizeBytes + dynamic_bytes <= (size_t)VR_LDS_CU ? hipSuccess : hipErrorInvalidValue;
 }
 
 template <int MODE, int DT, int INTERP>

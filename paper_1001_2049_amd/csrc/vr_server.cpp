@@ -183,9 +183,11 @@ static void server_loop(Server* S) {
                             ++itp;
                             continue;
                         }
-                        if (st == VR_ENOMEM) {  // can never fit beside what must stay resident
+                        if (st == VR_ENOMEM || st == VR_EUNSUPPORTED) {
+                            // can never fit beside what must stay resident, or a
+                            // cube larger than the budget (streamed by vr_render only)
                             tk.done = true;
-                            tk.status = VR_ENOMEM;
+                            tk.status = st;
                             tk.t_done = t;
                             drop_refs(c, tk);
                             itp = S->pending.erase(itp);

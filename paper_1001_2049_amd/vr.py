@@ -89,6 +89,14 @@ class vr_memory_stats(ctypes.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+class vr_progressive_info(ctypes.Structure):
+    _fields_ = [("level", ctypes.c_int32), ("converged", ctypes.c_int32), ("ms", ctypes.c_float),
+                ("predicted_ms", ctypes.c_float), ("samples_nominal", ctypes.c_uint64)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
 class vr_server_cfg(ctypes.Structure):
     _fields_ = [("max_batch_requests", ctypes.c_int32), ("max_batch_tiles", ctypes.c_int32),
                 ("max_inflight", ctypes.c_int32), ("use_graphs", ctypes.c_int32)]
@@ -122,6 +130,13 @@ _SIGNATURES = {
     "vr_set_camera": (S, [P, ctypes.POINTER(vr_camera)]),
     "vr_render": (S, [P, ctypes.c_int32, ctypes.POINTER(vr_render_params), P, P,
                       ctypes.POINTER(vr_stats)]),
+    "vr_render_progressive": (S, [P, ctypes.c_int32, ctypes.POINTER(vr_render_params),
+                                  ctypes.c_double, ctypes.c_int32, P, P,
+                                  ctypes.POINTER(vr_progressive_info)]),
+    "vr_render_subcube": (S, [P, ctypes.c_int32, ctypes.POINTER(vr_render_params), ctypes.c_int32,
+                              ctypes.c_int32, ctypes.c_int32, P, P, ctypes.POINTER(vr_stats)]),
+    "vr_composite": (S, [P, ctypes.c_int32, ctypes.POINTER(ctypes.c_void_p), ctypes.c_int32,
+                         ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, P, P]),
     "vr_render_noalloc": (S, [P, ctypes.c_int32, ctypes.POINTER(vr_render_params), P, P]),
     "vr_tf_create": (S, [P, P, ctypes.c_int32, ctypes.c_float, ctypes.c_float,
                          ctypes.POINTER(ctypes.c_int32)]),
@@ -435,6 +450,41 @@ class Renderer:
         check(lib().vr_render(self.ctx, cube, ctypes.byref(p), ctypes.c_void_p(out.data_ptr()),
                               self._stream(stream), ctypes.byref(st) if st is not None else None))
         return (out, st.as_dict()) if stats else out
+
+    def render_subcube(self, cube, width, height, axis, plane_lo, plane_hi, mode="ea",
+                       interp="trilinear", step=0.5, ert=0.99, use_skip=True, out=None,
+                       stream=None, stats=False):
+        """Partial image of the sub-cube of planes [plane_lo, plane_hi) on `axis`."""
+        p = make_params(width, height, mode, interp, step, ert, use_skip)
+        if out is None:
+            out = self.output(width, height, mode)
+        st = vr_stats() if stats else None
+        check(lib().vr_render_subcube(self.ctx, cube, ctypes.byref(p), int(axis), int(plane_lo),
+                                      int(plane_hi), ctypes.c_void_p(out.data_ptr()),
+                                      self._stream(stream),
+                                      ctypes.byref(st) if st is not None else None))
+        return (out, st.as_dict()) if stats else out
+
+    def composite(self, partials, axis, width, height, mode="ea", out=None, stream=None):
+        """Integrate partial images (sub-cubes in increasing plane order)."""
+        if out is None:
+            out = self.output(width, height, mode)
+        arr = (ctypes.c_void_p * len(partials))(*[t.data_ptr() for t in partials])
+        m = {"ea": VR_EA, "mip": VR_MIP}[mode] if isinstance(mode, str) else int(mode)
+        check(lib().vr_composite(self.ctx, m, arr, len(partials), int(axis), int(width),
+                                 int(height), ctypes.c_void_p(out.data_ptr()), self._stream(stream)))
+        return out
+
+    def render_progressive(self, cube, width, height, out, budget_ms, max_level=3, mode="ea",
+                           interp="trilinear", step=0.5, ert=0.99, use_skip=True, stream=None):
+        """One call of the coarse-to-fine loop (see vr_render_progressive); returns
+        its info as a dict."""
+        p = make_params(width, height, mode, interp, step, ert, use_skip)
+        info = vr_progressive_info()
+        check(lib().vr_render_progressive(self.ctx, cube, ctypes.byref(p), float(budget_ms),
+                                          int(max_level), ctypes.c_void_p(out.data_ptr()),
+                                          self._stream(stream), ctypes.byref(info)))
+        return info.as_dict()
 
     def request(self, cube, cam, width, height, out, mode="ea", interp="trilinear", step=0.5,
                 ert=0.99, use_skip=True, tf=0, clip=-math.inf) -> vr_request:

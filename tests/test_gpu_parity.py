@@ -1,6 +1,6 @@
 """GPU renderer vs the FP64 reference, element by element, through the C interface.
 
-Sizes span several 32x16-pixel workgroup tiles (512 threads), several 32^3 bricks and 8^3 skip
+Sizes span several 16x16-pixel workgroup tiles (256 threads), several 32^3 bricks and 8^3 skip
 cells, and ragged edges (image and cube sizes that are not multiples of the
 tile/brick/cell sizes).  Tolerances: max per-channel absolute error 1e-5 for
 float32 storage (RGBA in [0,1]); MIP values within 1e-5 * max(1, |m|);
@@ -385,3 +385,33 @@ def test_large_transfer_function_parity(R, tiny, tiny_cube):
     R.render_batch([R.request(tiny_cube, cam, 160, 120, out, mode="ea", clip=wl.clip_k)])
     torch.cuda.synchronize()
     assert np.array_equal(img.view(np.uint32), to_np(out).view(np.uint32))
+
+
+@pytest.mark.parametrize("mode", ["ea", "mip"])
+def test_rays_grazing_the_low_faces(R, mode):
+    """Rays that cross a cube only within half a voxel of its low x face
+    (positions in [-1/2, 0), which read voxel 0), in tiles whose other rays
+    lie further out: regression test for slab boxes that left out voxel 0.
+    The eye sits below and beside the cube; a z ramp makes every sample's
+    height visible in the MIP, and a noisy cube checks EA."""
+    ramp = np.arange(150, dtype=np.float32)[:, None, None] * np.ones((1, 64, 70), np.float32)
+    spec = synth.CubeSpec(70, 64, 150, seed=4040, sources=synth.SourcePop(8, 4, 30, True, 1.5, 6, 2, 20))
+    cam = synth.Camera(eye=(34.0, -40.0, -120.0), target=(34.5, 31.5, 74.5), up=(0.0, 0.0, 1.0),
+                       fovy_deg=40.0)
+    vol = ramp if mode == "mip" else synth.cube(spec)
+    cube = R.upload(vol, "f32")
+    try:
+        tf = synth.ramp_tf(256, 1.0)
+        R.set_transfer_function(tf, 3.0, 30.0)
+        R.set_noise_clip(-math.inf if mode == "mip" else 3.0, 1.0)
+        R.set_camera(cam)
+        got = to_np(R.render(cube, 180, 140, mode=mode))
+        kw = dict(tf=tf.astype(np.float64), v0=3.0, v1=30.0, clip=-math.inf if mode == "mip" else 3.0,
+                  step=0.5, ert=float(np.float32(0.99)))
+        ref = ref_render(vol, kw, cam, 180, 140, mode, "trilinear")
+        if mode == "ea":
+            compare_ea(got, ref["image"], TOL_F32, ref["flags"])
+        else:
+            compare_mip(got, ref["image"], TOL_F32, ref["flags"], ref.get("bounds"))
+    finally:
+        R.release(cube)

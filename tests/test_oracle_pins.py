@@ -688,3 +688,49 @@ def test_nearest_tie_bounds_are_the_candidate_maxima():
             if not tie:
                 assert lo == hi == img[j, i]
     assert ntie >= 8
+
+
+# ---------------------------------------------------------------------------
+# Sub-cube partials (Sec. 3.1, process steps 1, 4 and 5): windows along one
+# axis that tile it partition every ray's lattice; "over" of the EA partials in
+# visibility order and the maximum of the MIP partials give the whole image.
+# ---------------------------------------------------------------------------
+def _windows(n, cuts):
+    edges = [-np.inf] + [c - 0.5 for c in cuts] + [np.inf]
+    return list(zip(edges[:-1], edges[1:]))
+
+
+def test_subcube_partials_partition_and_compose():
+    spec = synth.CubeSpec(30, 26, 40, seed=77, sources=synth.SourcePop(4, 5, 20, False, 2, 5, 2, 6))
+    vol = synth.cube(spec)
+    tf = synth.ramp_tf(64, 1.0).astype(np.float64)
+    # eye below the cube along z: every ray that hits it moves up in z
+    cam = synth.Camera(eye=(14.0, -20.0, -45.0), target=(14.5, 12.5, 19.5), up=(0.0, 0.0, 1.0),
+                       fovy_deg=50.0)
+    common = dict(tf=tf, v0=3.0, v1=20.0, clip=3.0, step=0.5, ert=2.0, camera=cam, width=40,
+                  height=36)
+    whole = oracle.render(vol, mode=oracle.EA, **common)
+    wins = _windows(40, [7, 19, 32])
+    parts = [oracle.render(vol, mode=oracle.EA, window=(2, lo, hi), **common) for lo, hi in wins]
+    assert np.array_equal(sum(p["n_nominal"] for p in parts), whole["n_nominal"])
+    comp = oracle.composite_over([p["image"] for p in parts])
+    assert np.max(np.abs(comp - whole["image"])) < 1e-12
+    # back-to-front order is not the same image where partials overlap on a ray
+    wrong = oracle.composite_over([p["image"] for p in parts[::-1]])
+    assert np.max(np.abs(wrong - whole["image"])) > 1e-3
+    mwhole = oracle.render(vol, mode=oracle.MIP, **common)
+    mparts = [oracle.render(vol, mode=oracle.MIP, window=(2, lo, hi), **common)["image"] for lo, hi in wins]
+    assert np.array_equal(oracle.composite_max(mparts), mwhole["image"])
+
+
+def test_subcube_window_edges_are_flagged():
+    vol = np.zeros((8, 8, 8), np.float32)
+    cam = synth.axis_camera(8, 8, 8, "z", 8, 8)
+    # samples along z sit at -0.25 + 0.5k: a window edge at 1.75 meets one exactly
+    r = oracle.render(vol, mode=oracle.MIP, camera=cam, width=8, height=8, step=0.5,
+                      window=(2, -np.inf, 1.75))
+    assert np.all((r["flags"] & oracle.FLAG_WINDOW_AMBIG) > 0)
+    r = oracle.render(vol, mode=oracle.MIP, camera=cam, width=8, height=8, step=0.5,
+                      window=(2, -np.inf, 1.5))
+    assert not np.any((r["flags"] & oracle.FLAG_WINDOW_AMBIG) > 0)
+    assert np.all(r["n_nominal"] == 4)
