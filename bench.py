@@ -268,7 +268,7 @@ def measured_valu(kernel_name, width, samples, kernel_ms):
             "achieved": round(achieved / 1e12, 3), "peak": round(PEAK_VALU_LANE_INSTR / 1e12, 2),
             "unit": "T lane-instr/s", "frac": round(achieved / PEAK_VALU_LANE_INSTR, 4),
             "lds_instr_per_sample": float(kv.get("lds_instr_per_sample", "nan")),
-            "lds_bank_conflict_frac": float(kv.get("lds_bank_conflict_frac", "nan"))}
+            "lds_bank_conflict_cycles_per_lds_instr": float(kv.get("lds_bank_conflict_cycles_per_lds_instr", "nan"))}
 
 
 def measured_traffic(kernel_name, width):

@@ -266,6 +266,38 @@ __global__ void k_order_scatter_one(const DevReq R, int n, unsigned* hist, int* 
     }
 }
 
+// Small images: one workgroup buckets every tile, counts in LDS and scatters
+// (no global atomics, one launch instead of three).
+#define VR_ORDER_FUSED_WG 1024
+#define VR_ORDER_FUSED_MAX (16 * VR_ORDER_FUSED_WG)
+__global__ __launch_bounds__(VR_ORDER_FUSED_WG) void k_order_fused_one(const DevReq R, int n,
+                                                                       int* __restrict__ order) {
+    __shared__ unsigned hist[VR_NBUCKET], cur[VR_NBUCKET], off[VR_NBUCKET];
+    if (threadIdx.x < VR_NBUCKET) {
+        hist[threadIdx.x] = 0u;
+        cur[threadIdx.x] = 0u;
+    }
+    __syncthreads();
+    uint8_t bk[VR_ORDER_FUSED_MAX / VR_ORDER_FUSED_WG];
+#pragma unroll
+    for (int q = 0; q < VR_ORDER_FUSED_MAX / VR_ORDER_FUSED_WG; ++q) {
+        const int i = threadIdx.x + q * VR_ORDER_FUSED_WG;
+        bk[q] = 0;
+        if (i < n) {
+            const int b = tile_bucket(R, i);
+            bk[q] = (uint8_t)b;
+            atomicAdd(&hist[b], 1u);
+        }
+    }
+    __syncthreads();
+    order_offsets(hist, off);
+#pragma unroll
+    for (int q = 0; q < VR_ORDER_FUSED_MAX / VR_ORDER_FUSED_WG; ++q) {
+        const int i = threadIdx.x + q * VR_ORDER_FUSED_WG;
+        if (i < n) order[off[bk[q]] + atomicAdd(&cur[bk[q]], 1u)] = i;
+    }
+}
+
 __global__ void k_order_count_batch(const DevReq* __restrict__ reqs, const DevItem* __restrict__ items,
                                     const int* __restrict__ nitems, unsigned* hist) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -405,10 +437,14 @@ hipError_t vr_launch_render_batch(const DevReq* reqs, const DevItem* sorted, con
 hipError_t vr_launch_render(const DevReq& R, int* order, unsigned* hist, DevCounters* cnt,
                             hipStream_t s) {
     const int n = R.tiles_x * R.tiles_y;
-    const int ob = (n + 255) / 256;
-    hipLaunchKernelGGL(k_order_clear, dim3(1), dim3(2 * VR_NBUCKET), 0, s, hist);
-    hipLaunchKernelGGL(k_order_count_one, dim3(ob), dim3(256), 0, s, R, n, hist);
-    hipLaunchKernelGGL(k_order_scatter_one, dim3(ob), dim3(256), 0, s, R, n, hist, order);
+    if (n <= VR_ORDER_FUSED_MAX) {
+        hipLaunchKernelGGL(k_order_fused_one, dim3(1), dim3(VR_ORDER_FUSED_WG), 0, s, R, n, order);
+    } else {
+        const int ob = (n + 255) / 256;
+        hipLaunchKernelGGL(k_order_clear, dim3(1), dim3(2 * VR_NBUCKET), 0, s, hist);
+        hipLaunchKernelGGL(k_order_count_one, dim3(ob), dim3(256), 0, s, R, n, hist);
+        hipLaunchKernelGGL(k_order_scatter_one, dim3(ob), dim3(256), 0, s, R, n, hist, order);
+    }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     switch (R.mode * 10 + R.cube.dtype) {
