@@ -911,10 +911,12 @@ __device__ __forceinline__ bool tile_march(const DevReq& R, const Ray& ray, cons
     // [z][y][16-byte chunk] with np chunks per row and planes box_plane()
     // elements apart, and global->LDS loads write 16 bytes per lane at
     // consecutive LDS addresses, so each wave instruction moves rw = 64 / np
-    // whole rows, of one plane where planes are not contiguous (lane l: row
-    // l / np, chunk l % np; the x part of its source address stays fixed for
-    // the whole box).  Rows of more than 64 chunks go one row per instruction
-    // group.
+    // whole rows of one plane (lane l: row l / np, chunk l % np).  A voxel's
+    // pool address is the sum of a part that depends on its z only (the layer
+    // of bricks and the plane inside the slot) and a part that depends on its
+    // y and x only, so each lane computes its y/x part once per group of rows
+    // and the waves walk the planes with the z part alone (wave-uniform).
+    // Rows of more than 64 chunks go one row per instruction group.
     auto staged = [&](const Slab& s) { return s.elems <= (s.big ? 2 * cap : cap); };
     const uint32_t bstride = (uint32_t)R.cube.stride;
     auto row_src = [&](const Slab& s, int iy, int iz) -> const uint8_t* {
@@ -934,61 +936,52 @@ __device__ __forceinline__ bool tile_march(const DevReq& R, const Ray& ray, cons
         uint8_t* buf = boxes + s.boff;
         const int np = s.np, d1 = s.dim[1], d2 = s.dim[2];
         const int plane_bytes = box_plane<M, CV>(np, d1) * ELEM;
+        const uint64_t layer = (uint64_t)R.cube.by * R.cube.bx * bstride;  // bytes of a layer of bricks
         if (np <= 64) {
-            const float inv_np = 1.0f / (float)np;
-            const int rw = div_small(64, np, inv_np);
-            const int lr = div_small(lane, np, inv_np);
-            const bool on = lr < rw;
-            const uint64_t xo = chunk_off(s, lane - lr * np);
-            if (box_skew<M, CV>() != 0) {
-                // planes apart: groups of rw rows of one plane, one instruction each
-                const int gpp = div_small(d1 + rw - 1, rw, 1.0f / (float)rw);  // groups per plane
-                const float inv_gpp = 1.0f / (float)gpp;
-                for (int q = wave; q < gpp * d2; q += VR_NWAVE) {
-                    const int iz = div_small(q, gpp, inv_gpp);
-                    const int y0 = (q - iz * gpp) * rw;
-                    if (on && y0 + lr < d1)
-                        __builtin_amdgcn_global_load_lds((const void*)(row_src(s, y0 + lr, iz) + xo),
-                                                         (__attribute__((address_space(3))) void*)(buf + iz * plane_bytes + y0 * np * 16),
+            const int lo1 = __builtin_amdgcn_readfirstlane(s.lo[1]);
+            const int lo2 = __builtin_amdgcn_readfirstlane(s.lo[2]);
+            const int u1 = __builtin_amdgcn_readfirstlane(d1), u2 = __builtin_amdgcn_readfirstlane(d2);
+            const int unp = __builtin_amdgcn_readfirstlane(np);
+            const int upb = __builtin_amdgcn_readfirstlane(plane_bytes);
+            const int wv = __builtin_amdgcn_readfirstlane(wave);
+            uint8_t* const ubuf = boxes + __builtin_amdgcn_readfirstlane(s.boff);
+            const float inv_np = 1.0f / (float)unp;
+            const int rw = div_small(64, unp, inv_np);
+            const int lr = div_small(lane, unp, inv_np);
+            const uint64_t xo = chunk_off(s, lane - lr * unp);
+            const uint64_t brow = (uint64_t)R.cube.bx * bstride;  // bytes of a row of bricks
+            for (int y0 = 0; y0 < u1; y0 += rw) {
+                const int gy = min(lo1 + y0 + lr, N[1] - 1);
+                uint64_t yx = (uint64_t)(gy >> 5) * brow + (uint32_t)slot_y<DT>(gy & 31, R.cube.xch) * ELEM + xo;
+                asm volatile("" : "+v"(yx));  // one register pair, not re-summed per plane
+                const bool on = lr < rw && y0 + lr < u1;
+                for (int iz = wv; iz < u2; iz += VR_NWAVE) {
+                    const int gz = min(lo2 + iz, N[2] - 1);
+                    const int bzl = min(gz >> 5, R.cube.bz_hi - 1);  // plane 32 of a layer: its apron
+                    const uint8_t* zp = R.cube.pool + (uint64_t)bzl * layer +
+                                        (uint32_t)slot_z<DT>(gz - 32 * bzl, R.cube.xch) * ELEM;
+                    if (on)
+                        __builtin_amdgcn_global_load_lds((const void*)(zp + yx),
+                                                         (__attribute__((address_space(3))) void*)(ubuf + iz * upb + y0 * unp * 16),
                                                          16, 0, 0);
                 }
-                return;
             }
-            // contiguous planes: groups of rw consecutive rows, one instruction each
-            const int rows = d1 * d2;
-            const float inv_d1 = 1.0f / (float)d1;
-            const int rstep = VR_NWAVE * rw;
-            const int r_first = wave * rw + lr;
-            int iz = div_small(r_first, d1, inv_d1);
-            int iy = r_first - iz * d1;
-            const int dz = div_small(rstep, d1, inv_d1), dy = rstep - dz * d1;
-            for (int r0 = wave * rw; r0 < rows; r0 += rstep) {
-                if (on && r0 + lr < rows)
-                    __builtin_amdgcn_global_load_lds((const void*)(row_src(s, iy, iz) + xo),
-                                                     (__attribute__((address_space(3))) void*)(buf + r0 * np * 16),
+            return;
+        }
+        const int rows = d1 * d2;
+        const float inv_d1 = 1.0f / (float)d1;
+        for (int r = wave; r < rows; r += VR_NWAVE) {
+            const int iz = div_small(r, d1, inv_d1), iy = r - iz * d1;
+            const uint8_t* src = row_src(s, iy, iz);
+            for (int c0 = 0; c0 < np; c0 += 64) {
+                if (c0 + lane < np)
+                    __builtin_amdgcn_global_load_lds((const void*)(src + chunk_off(s, c0 + lane)),
+                                                     (__attribute__((address_space(3))) void*)(buf + iz * plane_bytes + (iy * np + c0) * 16),
                                                      16, 0, 0);
-                iy += dy;
-                iz += dz;
-                if (iy >= d1) {
-                    iy -= d1;
-                    ++iz;
-                }
-            }
-        } else {
-            const int rows = d1 * d2;
-            const float inv_d1 = 1.0f / (float)d1;
-            for (int r = wave; r < rows; r += VR_NWAVE) {
-                const int iz = div_small(r, d1, inv_d1), iy = r - iz * d1;
-                const uint8_t* src = row_src(s, iy, iz);
-                for (int c0 = 0; c0 < np; c0 += 64) {
-                    if (c0 + lane < np)
-                        __builtin_amdgcn_global_load_lds((const void*)(src + chunk_off(s, c0 + lane)),
-                                                         (__attribute__((address_space(3))) void*)(buf + iz * plane_bytes + (iy * np + c0) * 16),
-                                                         16, 0, 0);
-                }
             }
         }
     };
+
 
     // ---- prologue: slabs 0 and 1 ------------------------------------------------------
     if (wave == 0) {
