@@ -649,29 +649,19 @@ __device__ __forceinline__ Slab slab_box(int z0, int S, const Corners& cr, const
     return s;
 }
 
-// Thickest slab entered at plane ze, at most hi voxels, whose box holds at
-// most cap elements (bisection: the box only grows with the thickness);
-// ok = false when not even one voxel fits.
+// Thickest slab entered at plane ze, at most hi <= 64 voxels, whose box holds
+// at most cap elements; ok = false when not even one voxel fits.  Called by a
+// whole wave: lane l tries thickness l + 1, and as the box only grows with the
+// thickness, the lanes that fit are exactly those below the answer.
 template <int M, int CV>
 __device__ __forceinline__ Slab fit_slab(int ze, int sgn, int hi, int cap, const Corners& cr,
                                          const int N[3], const int CL[3], const int CH[3],
                                          int zmin, int zmax, bool& ok) {
-    Slab best = slab_box<M, CV>(sgn > 0 ? ze : ze - hi, hi, cr, N, CL, CH, zmin, zmax);
-    ok = true;
-    if (best.elems <= cap) return best;
-    int lo = 0;  // thickest known to fit (0: none); hi never fits
-    while (hi - lo > 1) {
-        const int mid = (lo + hi) >> 1;
-        const Slab m = slab_box<M, CV>(sgn > 0 ? ze : ze - mid, mid, cr, N, CL, CH, zmin, zmax);
-        if (m.elems <= cap) {
-            lo = mid;
-            best = m;
-        } else {
-            hi = mid;
-        }
-    }
-    ok = lo > 0;
-    return best;
+    const int t = min((int)(threadIdx.x & 63) + 1, hi);
+    const Slab m = slab_box<M, CV>(sgn > 0 ? ze : ze - t, t, cr, N, CL, CH, zmin, zmax);
+    const int S = min(__popcll(__ballot(m.elems <= cap)), hi);
+    ok = S > 0;
+    return slab_box<M, CV>(sgn > 0 ? ze : ze - max(S, 1), max(S, 1), cr, N, CL, CH, zmin, zmax);
 }
 
 // Next slab entered at plane ze: the thickest (at most twice the previous
