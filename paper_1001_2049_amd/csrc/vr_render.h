@@ -1259,33 +1259,47 @@ __device__ __forceinline__ bool render_tile(const DevReq& R, const int tx, const
         }
         sh.alive[0] = sh.alive[1] = sh.alive[2] = 0;
     }
-    // tile centre ray fixes the major axis; the corner rays bound the tile's rays
-    ff oc[3], dc[3];
-    ray_dir(R.cam, (float)(tx * VR_TW) + 0.5f * VR_TW, (float)(ty * VR_TH) + 0.5f * VR_TH, oc, dc);
-    const float ad0 = fabsf(dc[0].hi), ad1 = fabsf(dc[1].hi), ad2 = fabsf(dc[2].hi);
-    const int m = (ad2 > ad0 && ad2 > ad1) ? 2 : (ad1 > ad0 ? 1 : 0);
-    const float dm = m == 0 ? dc[0].hi : (m == 1 ? dc[1].hi : dc[2].hi);
-    const int sgn = dm > 0.0f ? 1 : -1;
-    const int m1 = m == 2 ? 0 : m + 1, m2 = m == 0 ? 2 : m - 1;
-    Corners cr;
-    bool ok = true;
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-        const float fi = (k & 1) ? (float)min(tx * VR_TW + VR_TW, R.W) - 0.5f : (float)(tx * VR_TW) + 0.5f;
-        const float fj = (k & 2) ? (float)min(ty * VR_TH + VR_TH, R.H) - 0.5f : (float)(ty * VR_TH) + 0.5f;
+    // tile centre ray fixes the major axis; the corner rays bound the tile's
+    // rays.  Lane k < 5 of each wave builds ray k (corners 0..3, centre 4) and
+    // the values are broadcast, so the tile's geometry lives in scalar registers.
+    const int lane = tid & 63, k5 = lane % 5;
+    float o3[3], d3[3];
+    {
+        const float fi = k5 == 4 ? (float)(tx * VR_TW) + 0.5f * VR_TW
+                                 : ((k5 & 1) ? (float)min(tx * VR_TW + VR_TW, R.W) - 0.5f : (float)(tx * VR_TW) + 0.5f);
+        const float fj = k5 == 4 ? (float)(ty * VR_TH) + 0.5f * VR_TH
+                                 : ((k5 & 2) ? (float)min(ty * VR_TH + VR_TH, R.H) - 0.5f : (float)(ty * VR_TH) + 0.5f);
         ff o[3], d[3];
         ray_dir(R.cam, fi, fj, o, d);
-        const float o3[3] = {ff_to_f(o[0]), ff_to_f(o[1]), ff_to_f(o[2])};
-        const float d3[3] = {d[0].hi, d[1].hi, d[2].hi};
-        const float dmk = m == 0 ? d3[0] : (m == 1 ? d3[1] : d3[2]);
-        const float omk = m == 0 ? o3[0] : (m == 1 ? o3[1] : o3[2]);
-        ok = ok && (float)sgn * dmk >= 0.25f;
-        const float r1 = (m1 == 0 ? d3[0] : (m1 == 1 ? d3[1] : d3[2])) / dmk;
-        const float r2 = (m2 == 0 ? d3[0] : (m2 == 1 ? d3[1] : d3[2])) / dmk;
-        cr.r[k][0] = r1;
-        cr.r[k][1] = r2;
-        cr.c[k][0] = (m1 == 0 ? o3[0] : (m1 == 1 ? o3[1] : o3[2])) - omk * r1;
-        cr.c[k][1] = (m2 == 0 ? o3[0] : (m2 == 1 ? o3[1] : o3[2])) - omk * r2;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            o3[a] = ff_to_f(o[a]);
+            d3[a] = d[a].hi;
+        }
+    }
+    auto bcast = [](float v, int l) {
+        return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), l));
+    };
+    const float dc0 = bcast(d3[0], 4), dc1 = bcast(d3[1], 4), dc2 = bcast(d3[2], 4);
+    const float ad0 = fabsf(dc0), ad1 = fabsf(dc1), ad2 = fabsf(dc2);
+    const int m = (ad2 > ad0 && ad2 > ad1) ? 2 : (ad1 > ad0 ? 1 : 0);
+    const float dm = m == 0 ? dc0 : (m == 1 ? dc1 : dc2);
+    const int sgn = dm > 0.0f ? 1 : -1;
+    const int m1 = m == 2 ? 0 : m + 1, m2 = m == 0 ? 2 : m - 1;
+    const float dmk = m == 0 ? d3[0] : (m == 1 ? d3[1] : d3[2]);
+    const float omk = m == 0 ? o3[0] : (m == 1 ? o3[1] : o3[2]);
+    const float r1 = (m1 == 0 ? d3[0] : (m1 == 1 ? d3[1] : d3[2])) / dmk;
+    const float r2 = (m2 == 0 ? d3[0] : (m2 == 1 ? d3[1] : d3[2])) / dmk;
+    const float c1 = (m1 == 0 ? o3[0] : (m1 == 1 ? o3[1] : o3[2])) - omk * r1;
+    const float c2 = (m2 == 0 ? o3[0] : (m2 == 1 ? o3[1] : o3[2])) - omk * r2;
+    const bool ok = (__ballot(k5 < 4 && lane < 5 && (float)sgn * dmk >= 0.25f) & 0xfull) == 0xfull;
+    Corners cr;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        cr.r[k][0] = bcast(r1, k);
+        cr.r[k][1] = bcast(r2, k);
+        cr.c[k][0] = bcast(c1, k);
+        cr.c[k][1] = bcast(c2, k);
     }
     if (!ok) return false;
     Ray ray;
@@ -1306,6 +1320,8 @@ __device__ __forceinline__ void render_tile_any(const DevReq& R, const int tx, c
                                                 uint8_t* __restrict__ boxes, TileShared& sh,
                                                 LaneCounts& cnt) {
     if (render_tile<MODE, DT, INTERP>(R, tx, ty, tfl, boxes, sh, cnt)) return;
+    __builtin_amdgcn_s_waitcnt(0);  // transfer-function rows have landed
+    __syncthreads();
     int px, py;
     tile_pixel(R, tx, ty, px, py);
     if (px < R.W && py < R.H) render_lane_direct<MODE, DT, INTERP>(R, px, py, tfl, cnt);
@@ -1328,6 +1344,17 @@ __device__ __forceinline__ void flush_counts(const LaneCounts& c, DevCounters* c
     }
 }
 
+// Transfer-function rows (n x 32 bytes) copied into LDS with global->LDS loads
+// (16 bytes per lane at consecutive LDS addresses).  Nothing waits for them
+// here: the first slab's wait for its box copy (or the fallback walker's wait)
+// covers them, so their latency overlaps the tile's set-up.
+__device__ __forceinline__ void tf_stage(const DevReq& R, float4* lds4) {
+    const float4* rows = (const float4*)R.tf.rows;
+    for (int e = threadIdx.x; e < 2 * R.tf.n; e += VR_WG)
+        __builtin_amdgcn_global_load_lds((const void*)(rows + e),
+                                         (__attribute__((address_space(3))) void*)(lds4 + e), 16, 0, 0);
+}
+
 // dynamic LDS: transfer-function rows (n x 32 bytes), then two slab boxes
 template <int MODE, int DT, int INTERP>
 __global__ __launch_bounds__(VR_WG, VR_WAVES_PER_EU) void k_render(const DevReq R, const int* __restrict__ order,
@@ -1338,10 +1365,7 @@ __global__ __launch_bounds__(VR_WG, VR_WAVES_PER_EU) void k_render(const DevReq 
     float* tfl = (float*)lds4;
     // EA: transfer-function rows; MIP: cell bounds of running-maximum skipping
     const int tf_bytes = MODE == 0 ? 32 * R.tf.n : VR_MIPC_BYTES;
-    if (MODE == 0) {
-        const float4* rows = (const float4*)R.tf.rows;
-        for (int e = threadIdx.x; e < 2 * R.tf.n; e += VR_WG) lds4[e] = rows[e];
-    }
+    if (MODE == 0) tf_stage(R, lds4);
     if (cnt && threadIdx.x < 5) wgc[threadIdx.x] = 0u;
     __syncthreads();
     const int tile = order[blockIdx.x];

@@ -38,10 +38,7 @@ __global__ __launch_bounds__(VR_WG, VR_WAVES_PER_EU) void k_render_batch(const D
         if (it >= nitems) break;
         const DevItem item = items[it];
         const DevReq& R = reqs[item.req];
-        if (R.mode == 0) {
-            const float4* rows = (const float4*)R.tf.rows;
-            for (int e = threadIdx.x; e < 2 * R.tf.n; e += VR_WG) lds4[e] = rows[e];
-        }
+        if (R.mode == 0) tf_stage(R, lds4);
         __syncthreads();
         const int tx = item.tile % R.tiles_x, ty = item.tile / R.tiles_x;
         LaneCounts c = {0u, 0u, 0u, 0u, 0u};
