@@ -29,7 +29,7 @@ L2_FILE = os.path.join(ROOT, "profiles", "k_render_full512_l2.txt")
 SQ_FILE = os.path.join(ROOT, "profiles", "k_render_full512_sq.txt")
 # sources that define the render kernels: committed counter summaries carry
 # their digest and are used only while it matches
-KERNEL_SOURCES = ["vr_common.h", "vr_dev.h", "vr_render.h", "vr_render_batch.hip",
+KERNEL_SOURCES = ["vr_common.h", "vr_dev.h", "vr_render.h",
                   "vr_render_ea_f32.hip", "vr_render_ea_f16.hip", "vr_render_ea_bf16.hip",
                   "vr_render_mip_f32.hip", "vr_render_mip_f16.hip", "vr_render_mip_bf16.hip"]
 

@@ -17,7 +17,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(os.path.dirname(HERE), "include")
 LIB = os.path.join(HERE, "libvr.so")
-SOURCES = ["vr_render_batch.hip", "vr_render_ea_f32.hip", "vr_render_ea_f16.hip",
+SOURCES = ["vr_render_ea_f32.hip", "vr_render_ea_f16.hip",
            "vr_render_ea_bf16.hip", "vr_render_mip_f32.hip", "vr_render_mip_f16.hip",
            "vr_render_mip_bf16.hip", "vr_kernels.hip", "vr_noise.hip", "vr_capi.cpp",
            "vr_server.cpp", "vr_noalloc.cpp", "vr_subcube.hip"]

@@ -526,7 +526,6 @@ void free_batch_bufs(Ctx* c, BatchBufs& bb) {
     dev_free(c, bb.head, false);
     dev_free(c, bb.hdr, false);
     dev_free(c, bb.sorted, false);
-    dev_free(c, bb.hist, false);
     if (bb.pin_reqs) (void)hipHostFree(bb.pin_reqs);
     if (bb.pin_items) (void)hipHostFree(bb.pin_items);
     if (bb.pin_hdr) (void)hipHostFree(bb.pin_hdr);
@@ -554,7 +553,6 @@ static vr_status grow_batch(Ctx* c, BatchBufs& bb, int nreq, int nitems) {
     if (!bb.head.ptr) {
         st = dev_alloc(c, bb.head, 256, false);
         if (st == VR_OK) st = dev_alloc(c, bb.hdr, 256, false);
-        if (st == VR_OK) st = dev_alloc(c, bb.hist, 1024, false);
         if (st == VR_OK)
             st = hip_check(hipHostMalloc((void**)&bb.pin_hdr, 256, 0), "hipHostMalloc");
         if (st != VR_OK) return st;
@@ -598,16 +596,25 @@ static vr_status grow_batch(Ctx* c, BatchBufs& bb, int nreq, int nitems) {
     return VR_OK;
 }
 
-// copies + reset + batch kernel, either enqueued directly or captured once
+static int log2_of(int v) {
+    int k = 0;
+    while ((1 << k) < v) ++k;
+    return k;
+}
+
+// copies + ordering + one persistent launch per batch class present, either
+// enqueued directly or captured once per (buffer sizes, LDS, classes)
 static vr_status enqueue_batch(Ctx* c, BatchBufs& bb, int count, int nitems, size_t lds,
-                               DevCounters* dev_counters, hipStream_t s, bool use_graph) {
+                               unsigned class_mask, DevCounters* dev_counters, hipStream_t s,
+                               bool use_graph) {
     const size_t rq_bytes = (size_t)(use_graph ? bb.reqs_cap : count) * sizeof(DevReq);
     const size_t it_bytes = (size_t)(use_graph ? bb.items_cap : nitems) * sizeof(DevItem);
     const int slots = c->num_cu * VR_WG_PER_CU;  // resident workgroups
     const int grid = use_graph ? slots : std::max(1, std::min(nitems, slots));
     g_stage = "batch enqueue";
     auto record = [&]() -> vr_status {
-        vr_status st = hip_check(hipMemcpyAsync(bb.hdr.ptr, bb.pin_hdr, 16, hipMemcpyHostToDevice, s),
+        vr_status st = hip_check(hipMemcpyAsync(bb.hdr.ptr, bb.pin_hdr, (3 + VR_NCLASS) * sizeof(int),
+                                                hipMemcpyHostToDevice, s),
                                  "hipMemcpyAsync");
         if (st == VR_OK)
             st = hip_check(hipMemcpyAsync(bb.reqs.ptr, bb.pin_reqs, rq_bytes, hipMemcpyHostToDevice, s),
@@ -617,14 +624,16 @@ static vr_status enqueue_batch(Ctx* c, BatchBufs& bb, int count, int nitems, siz
                            "hipMemcpyAsync");
         if (st == VR_OK)
             st = hip_check(vr_launch_batch((const DevReq*)bb.reqs.ptr, (const DevItem*)bb.items.ptr,
-                                           (const int*)bb.hdr.ptr, use_graph ? bb.items_cap : nitems,
-                                           (DevItem*)bb.sorted.ptr, (unsigned*)bb.hist.ptr,
-                                           (unsigned*)bb.head.ptr, dev_counters, lds, grid, s),
+                                           (const int*)bb.hdr.ptr, use_graph ? bb.reqs_cap : count,
+                                           class_mask, (DevItem*)bb.sorted.ptr, (unsigned*)bb.head.ptr,
+                                           dev_counters, lds, grid, s),
                            "batch launch");
         return st;
     };
     if (!use_graph) return record();
-    const uint64_t key = ((uint64_t)bb.items_cap << 40) ^ ((uint64_t)bb.reqs_cap << 24) ^ (uint64_t)lds;
+    // capacities are powers of two, LDS < 2^20 bytes
+    const uint64_t key = ((uint64_t)log2_of(bb.items_cap) << 40) | ((uint64_t)log2_of(bb.reqs_cap) << 34) |
+                         ((uint64_t)class_mask << 20) | (uint64_t)lds;
     auto it = bb.graphs.find(key);
     if (it == bb.graphs.end()) {
         vr_status st = hip_check(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal),
@@ -678,18 +687,29 @@ vr_status launch_requests(Ctx* c, BatchBufs& bb, const vr_request* reqs, int cou
                            &used[(size_t)r]);
         if (st != VR_OK) return st;
         if (tf) max_tf_n = std::max(max_tf_n, tf->n);
-        const DevReq& R = bb.pin_reqs[r];
-        const int t0 = tiles ? tiles[2 * r] : 0;
-        const int t1 = tiles ? tiles[2 * r + 1] : R.tiles_x * R.tiles_y;
-        for (int t = t0; t < t1; ++t) bb.pin_items[k++] = DevItem{r, t};
     }
+    // work list: the items of each batch class in one run, requests in order
+    unsigned class_mask = 0u;
+    for (int cls = 0; cls < VR_NCLASS; ++cls) {
+        bb.pin_hdr[2 + cls] = k;
+        for (int r = 0; r < count; ++r) {
+            const DevReq& R = bb.pin_reqs[r];
+            if (VR_BATCH_CLASS(R.mode, R.cube.dtype, R.interp) != cls) continue;
+            const int t0 = tiles ? tiles[2 * r] : 0;
+            const int t1 = tiles ? tiles[2 * r + 1] : R.tiles_x * R.tiles_y;
+            for (int t = t0; t < t1; ++t) bb.pin_items[k++] = DevItem{r, t};
+            if (t1 > t0) class_mask |= 1u << cls;
+        }
+    }
+    bb.pin_hdr[2 + VR_NCLASS] = k;
     // shape class: the TF table size fixes the LDS split (256-row tables share one class)
     if (use_graph) max_tf_n = std::max(max_tf_n, 256);
     for (int r = 0; r < count; ++r) bb.pin_reqs[r].box_bytes = vr_box_bytes(max_tf_n);
     bb.pin_hdr[0] = nitems;
+    bb.pin_hdr[1] = count;
     if (nitems > 0) {
         const size_t lds = (size_t)vr_lds_reserve(max_tf_n) + 2 * (size_t)vr_box_bytes(max_tf_n);
-        st = enqueue_batch(c, bb, count, nitems, lds, dev_counters, s, use_graph);
+        st = enqueue_batch(c, bb, count, nitems, lds, class_mask, dev_counters, s, use_graph);
         if (st != VR_OK) return st;
     }
     g_stage = "batch completion";

@@ -48,6 +48,10 @@ struct ff {
 #define VR_MIPC (768 / VR_WG_PER_CU)          // cells per slab box
 #define VR_MIPC_BYTES (3 * VR_MIPC * 4)
 #define VR_TROW 16                            // cells per box row (longer rows: no skipping)
+// Batch class of a request: its kernel specialisation (mode, storage,
+// interpolation); a batch runs one persistent launch per class present.
+#define VR_NCLASS 12
+#define VR_BATCH_CLASS(mode, dtype, interp) ((mode) * 6 + (dtype) * 2 + (interp))
 #define VR_MAX_PARTIALS 64                    // sub-cube partials per composite
 #define VR_PROG_LEVELS 5                      // progressive rendering: levels 0 .. 4
 // Waves of the render kernels per SIMD (what the register budget must allow).

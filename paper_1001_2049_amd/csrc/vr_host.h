@@ -105,13 +105,13 @@ struct Server;
 // graphs captured over those buffers (one per shape class).
 struct BatchBufs {
     DevBuf reqs, items, head, hdr;
-    DevBuf sorted, hist;  // work list reordered most expensive first; bucket counts
+    DevBuf sorted;  // work list, each request's tiles most expensive first
     DevReq* pin_reqs = nullptr;
     DevItem* pin_items = nullptr;
     int* pin_hdr = nullptr;
     int reqs_cap = 0, items_cap = 0;
     hipEvent_t done = nullptr;  // staging is reusable once this has fired
-    std::map<uint64_t, hipGraphExec_t> graphs;  // key: (items class, requests class, LDS bytes)
+    std::map<uint64_t, hipGraphExec_t> graphs;  // key: (items class, requests class, batch classes, LDS bytes)
 };
 
 struct Ctx {

@@ -298,30 +298,68 @@ __global__ __launch_bounds__(VR_ORDER_FUSED_WG) void k_order_fused_one(const Dev
     }
 }
 
-__global__ void k_order_count_batch(const DevReq* __restrict__ reqs, const DevItem* __restrict__ items,
-                                    const int* __restrict__ nitems, unsigned* hist) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < *nitems) {
-        const DevItem it = items[i];
-        atomicAdd(&hist[tile_bucket(reqs[it.req], it.tile)], 1u);
+// Batches: the work list holds the items of each batch class in one run
+// (hdr[2 + k] .. hdr[3 + k] for class k), requests in order inside it.  One
+// workgroup per request orders that request's items (found by binary search
+// on the request index inside its class's run) most expensive first, in runs
+// of up to VR_ORDER_FUSED_MAX items, so each class's persistent launch takes
+// its requests one after another, each in longest-first order.
+// hdr[1]: requests.
+__global__ __launch_bounds__(VR_ORDER_FUSED_WG) void k_order_fused_batch(const DevReq* __restrict__ reqs,
+                                                                         const DevItem* __restrict__ items,
+                                                                         const int* __restrict__ hdr,
+                                                                         DevItem* __restrict__ sorted) {
+    __shared__ unsigned hist[VR_NBUCKET], cur[VR_NBUCKET], off[VR_NBUCKET];
+    __shared__ int rng[2];
+    const int r = blockIdx.x;
+    if (r >= hdr[1]) return;
+    const DevReq& R = reqs[r];
+    const int cls = VR_BATCH_CLASS(R.mode, R.cube.dtype, R.interp);
+    if (threadIdx.x < 2) {
+        const int key = r + (int)threadIdx.x;  // first item of request r, of request r + 1
+        int lo = hdr[2 + cls], hi = hdr[3 + cls];
+        while (lo < hi) {
+            const int mid = (lo + hi) >> 1;
+            if (items[mid].req < key)
+                lo = mid + 1;
+            else
+                hi = mid;
+        }
+        rng[threadIdx.x] = lo;
     }
-}
-
-__global__ void k_order_scatter_batch(const DevReq* __restrict__ reqs, const DevItem* __restrict__ items,
-                                      const int* __restrict__ nitems, unsigned* hist,
-                                      DevItem* __restrict__ sorted) {
-    __shared__ unsigned off[VR_NBUCKET];
-    order_offsets(hist, off);
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < *nitems) {
-        const DevItem it = items[i];
-        const int b = tile_bucket(reqs[it.req], it.tile);
-        sorted[off[b] + atomicAdd(&hist[VR_NBUCKET + b], 1u)] = it;
+    __syncthreads();
+    const int b0 = rng[0], b1 = rng[1];
+    for (int c0 = b0; c0 < b1; c0 += VR_ORDER_FUSED_MAX) {
+        const int n = min(VR_ORDER_FUSED_MAX, b1 - c0);
+        if (threadIdx.x < VR_NBUCKET) {
+            hist[threadIdx.x] = 0u;
+            cur[threadIdx.x] = 0u;
+        }
+        __syncthreads();
+        uint8_t bk[VR_ORDER_FUSED_MAX / VR_ORDER_FUSED_WG];
+#pragma unroll
+        for (int q = 0; q < VR_ORDER_FUSED_MAX / VR_ORDER_FUSED_WG; ++q) {
+            const int i = threadIdx.x + q * VR_ORDER_FUSED_WG;
+            bk[q] = 0;
+            if (i < n) {
+                const int b = tile_bucket(R, items[c0 + i].tile);
+                bk[q] = (uint8_t)b;
+                atomicAdd(&hist[b], 1u);
+            }
+        }
+        __syncthreads();
+        order_offsets(hist, off);
+#pragma unroll
+        for (int q = 0; q < VR_ORDER_FUSED_MAX / VR_ORDER_FUSED_WG; ++q) {
+            const int i = threadIdx.x + q * VR_ORDER_FUSED_WG;
+            if (i < n) sorted[c0 + off[bk[q]] + atomicAdd(&cur[bk[q]], 1u)] = items[c0 + i];
+        }
+        __syncthreads();
     }
 }
 
 __global__ void k_reset_head(unsigned* head) {
-    if (threadIdx.x == 0 && blockIdx.x == 0) *head = 0u;
+    if (threadIdx.x < VR_NCLASS && blockIdx.x == 0) head[threadIdx.x] = 0u;
 }
 
 // ---------------------------------------------------------------------------
@@ -430,9 +468,15 @@ hipError_t vr_launch_render_0_2(const DevReq&, const int*, DevCounters*, hipStre
 hipError_t vr_launch_render_1_0(const DevReq&, const int*, DevCounters*, hipStream_t);
 hipError_t vr_launch_render_1_1(const DevReq&, const int*, DevCounters*, hipStream_t);
 hipError_t vr_launch_render_1_2(const DevReq&, const int*, DevCounters*, hipStream_t);
-hipError_t vr_launch_render_batch(const DevReq* reqs, const DevItem* sorted, const int* nitems,
-                                  unsigned* head, DevCounters* cnt, size_t lds_bytes, int grid,
-                                  hipStream_t s);
+#define VR_BATCH_LAUNCHER_DECL(MODE, DT)                                                          \
+    hipError_t vr_launch_batch_##MODE##_##DT(const DevReq*, const DevItem*, const int*, int, unsigned*, \
+                                             DevCounters*, size_t, int, hipStream_t);
+VR_BATCH_LAUNCHER_DECL(0, 0)
+VR_BATCH_LAUNCHER_DECL(0, 1)
+VR_BATCH_LAUNCHER_DECL(0, 2)
+VR_BATCH_LAUNCHER_DECL(1, 0)
+VR_BATCH_LAUNCHER_DECL(1, 1)
+VR_BATCH_LAUNCHER_DECL(1, 2)
 
 hipError_t vr_launch_render(const DevReq& R, int* order, unsigned* hist, DevCounters* cnt,
                             hipStream_t s) {
@@ -458,16 +502,24 @@ hipError_t vr_launch_render(const DevReq& R, int* order, unsigned* hist, DevCoun
     }
 }
 
-hipError_t vr_launch_batch(const DevReq* reqs, const DevItem* items, const int* nitems,
-                           int items_cap, DevItem* sorted, unsigned* hist, unsigned* head,
-                           DevCounters* cnt, size_t lds_bytes, int grid, hipStream_t s) {
-    const int ob = (items_cap + 255) / 256;
-    hipLaunchKernelGGL(k_order_clear, dim3(1), dim3(2 * VR_NBUCKET), 0, s, hist);
-    hipLaunchKernelGGL(k_order_count_batch, dim3(ob), dim3(256), 0, s, reqs, items, nitems, hist);
-    hipLaunchKernelGGL(k_order_scatter_batch, dim3(ob), dim3(256), 0, s, reqs, items, nitems, hist,
-                       sorted);
+hipError_t vr_launch_batch(const DevReq* reqs, const DevItem* items, const int* hdr, int reqs_grid,
+                           unsigned class_mask, DevItem* sorted, unsigned* head, DevCounters* cnt,
+                           size_t lds_bytes, int grid, hipStream_t s) {
+    hipLaunchKernelGGL(k_order_fused_batch, dim3(reqs_grid), dim3(VR_ORDER_FUSED_WG), 0, s, reqs, items,
+                       hdr, sorted);
     hipLaunchKernelGGL(k_reset_head, dim3(1), dim3(64), 0, s, head);
     hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    return vr_launch_render_batch(reqs, sorted, nitems, head, cnt, lds_bytes, grid, s);
+    for (int k = 0; k < VR_NCLASS && e == hipSuccess; ++k) {
+        if (!(class_mask >> k & 1u)) continue;
+        const int mode = k / 6, dt = (k / 2) % 3, interp = k % 2;
+        switch (mode * 10 + dt) {
+            case 0: e = vr_launch_batch_0_0(reqs, sorted, hdr, interp, head, cnt, lds_bytes, grid, s); break;
+            case 1: e = vr_launch_batch_0_1(reqs, sorted, hdr, interp, head, cnt, lds_bytes, grid, s); break;
+            case 2: e = vr_launch_batch_0_2(reqs, sorted, hdr, interp, head, cnt, lds_bytes, grid, s); break;
+            case 10: e = vr_launch_batch_1_0(reqs, sorted, hdr, interp, head, cnt, lds_bytes, grid, s); break;
+            case 11: e = vr_launch_batch_1_1(reqs, sorted, hdr, interp, head, cnt, lds_bytes, grid, s); break;
+            default: e = vr_launch_batch_1_2(reqs, sorted, hdr, interp, head, cnt, lds_bytes, grid, s); break;
+        }
+    }
+    return e;
 }

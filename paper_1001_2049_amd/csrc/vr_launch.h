@@ -54,11 +54,21 @@ hipError_t vr_launch_classify(const float* cell_minmax, uint64_t* mask, uint32_t
 hipError_t vr_launch_render(const DevReq& R, int* order, unsigned* hist, DevCounters* cnt,
                             hipStream_t s);
 
-// Many images in one persistent launch over a (request, tile) work list of
-// *nitems entries (read on the device, so a captured launch serves any count),
-// reordered most expensive first into `sorted` (items_cap entries); hist: 256 words.
+// Many images in persistent launches over a (request, tile) work list,
+// one launch per batch class present (bit k of class_mask: class k, see
+// VR_BATCH_CLASS).  The list holds each class's items in one run, requests in
+// order inside it; hdr (device, read there so a captured launch serves any
+// count): [1] requests, [2 + k] first item of class k, [2 + VR_NCLASS] all
+// items.  Each request's tiles are reordered most expensive first into
+// `sorted`; reqs_grid: workgroups of the ordering kernel (at least the
+// requests); head: VR_NCLASS counters.
+hipError_t vr_launch_batch(const DevReq* reqs, const DevItem* items, const int* hdr, int reqs_grid,
+                           unsigned class_mask, DevItem* sorted, unsigned* head, DevCounters* cnt,
+                           size_t lds_bytes, int grid, hipStream_t s);
+// reqs_grid: workgroups of the ordering kernel (at least the requests);
+// hist: 256 words.
 hipError_t vr_launch_batch(const DevReq* reqs, const DevItem* items, const int* nitems,
-                           int items_cap, DevItem* sorted, unsigned* hist, unsigned* head,
+                           int items_cap, int reqs_grid, DevItem* sorted, unsigned* hist, unsigned* head,
                            DevCounters* cnt, size_t lds_bytes, int grid, hipStream_t s);
 
 // Nearest-neighbour enlargement of a (W >> L) x (H >> L) image (rounded up)

@@ -1394,10 +1394,62 @@ static hipError_t launch_r(const DevReq& R, const int* order, DevCounters* cnt, 
     return hipGetLastError();
 }
 
-// Defines the launcher of one (mode, storage) pair, both interpolations.
+// Persistent grid over the (request, tile) items of one batch class: items
+// [hdr[2 + cls], hdr[3 + cls]) of the ordered work list, taken one at a time
+// through the class's counter.  Which workgroup renders a tile never changes
+// the tile's pixels.
+template <int MODE, int DT, int INTERP>
+__global__ __launch_bounds__(VR_WG, VR_WAVES_PER_EU) void k_render_batch(const DevReq* __restrict__ reqs,
+                                                                         const DevItem* __restrict__ items,
+                                                                         const int* __restrict__ hdr, int cls,
+                                                                         unsigned* head, DevCounters* cnt) {
+    extern __shared__ float4 lds4[];
+    __shared__ int s_item;
+    __shared__ unsigned wgc[5];
+    __shared__ TileShared sh;
+    float* tfl = (float*)lds4;
+    const int i0 = hdr[2 + cls], i1 = hdr[3 + cls];
+    for (;;) {
+        if (threadIdx.x == 0) s_item = i0 + (int)atomicAdd(head, 1u);
+        if (cnt && threadIdx.x < 5) wgc[threadIdx.x] = 0u;
+        __syncthreads();
+        const int it = s_item;
+        if (it >= i1) break;
+        const DevItem item = items[it];
+        const DevReq& R = reqs[item.req];
+        if (MODE == 0) tf_stage(R, lds4);
+        const int tx = item.tile % R.tiles_x, ty = item.tile / R.tiles_x;
+        LaneCounts c = {0u, 0u, 0u, 0u, 0u};
+        uint8_t* boxes = (uint8_t*)tfl + (MODE == 0 ? 32 * R.tf.n : VR_MIPC_BYTES);
+        render_tile_any<MODE, DT, INTERP>(R, tx, ty, tfl, boxes, sh, c);
+        if (cnt) flush_counts(c, cnt + item.req, wgc);
+        __syncthreads();
+    }
+}
+
+template <int MODE, int DT, int INTERP>
+static hipError_t launch_b(const DevReq* reqs, const DevItem* sorted, const int* hdr, int cls,
+                           unsigned* head, DevCounters* cnt, size_t lds, int grid, hipStream_t s) {
+    const hipError_t e = check_lds((const void*)k_render_batch<MODE, DT, INTERP>, lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((k_render_batch<MODE, DT, INTERP>), dim3(grid), dim3(VR_WG), lds, s, reqs, sorted,
+                       hdr, cls, head + cls, cnt);
+    return hipGetLastError();
+}
+
+// Defines the launchers of one (mode, storage) pair, both interpolations: the
+// single image and the batch class.
 #define VR_RENDER_LAUNCHER(MODE, DT)                                                          \
     hipError_t vr_launch_render_##MODE##_##DT(const DevReq& R, const int* order,               \
                                               DevCounters* cnt, hipStream_t s) {              \
         return R.interp == 1 ? launch_r<MODE, DT, 1>(R, order, cnt, s)                         \
                              : launch_r<MODE, DT, 0>(R, order, cnt, s);                        \
+    }                                                                                          \
+    hipError_t vr_launch_batch_##MODE##_##DT(const DevReq* reqs, const DevItem* sorted,        \
+                                             const int* hdr, int interp, unsigned* head,       \
+                                             DevCounters* cnt, size_t lds, int grid,           \
+                                             hipStream_t s) {                                  \
+        const int cls = VR_BATCH_CLASS(MODE, DT, interp);                                      \
+        return interp == 1 ? launch_b<MODE, DT, 1>(reqs, sorted, hdr, cls, head, cnt, lds, grid, s) \
+                           : launch_b<MODE, DT, 0>(reqs, sorted, hdr, cls, head, cnt, lds, grid, s); \
     }

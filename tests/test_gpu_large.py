@@ -74,16 +74,30 @@ def test_large_cube_sampled_pixels(large, mode):
 
 
 def test_large_orbit_batch_equals_single(large):
+    """The 64-view orbit in one persistent launch and as 64 single launches on
+    the same views: every view bit-identical, both timed with HIP events."""
     import torch
     wl, r, cube, codes, tf = large
     W = H = wl.width
     outs = [r.output(W, H, "ea") for _ in range(64)]
     reqs = [r.request(cube, orbit64(wl.cube, i, W), W, H, outs[i], mode="ea", clip=wl.clip_k)
             for i in range(64)]
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
     r.render_batch(reqs)
+    e1.record()
     torch.cuda.synchronize()
-    for i in (0, 21, 63):
+    batch_ms = e0.elapsed_time(e1)
+    single = r.output(W, H, "ea")
+    single_ms = []
+    for i in range(64):
         r.set_camera(orbit64(wl.cube, i, W))
-        single = r.render(cube, W, H, mode="ea")
+        e0.record()
+        r.render(cube, W, H, mode="ea", out=single)
+        e1.record()
         torch.cuda.synchronize()
+        single_ms.append(e0.elapsed_time(e1))
         assert torch.equal(single.view(torch.int32), outs[i].view(torch.int32)), i
+    print("large orbit: one batched launch %.1f ms (%.2f ms per view); 64 single launches %.1f ms "
+          "(%.2f ms per view, min %.2f, max %.2f)" % (batch_ms, batch_ms / 64, sum(single_ms),
+                                                      sum(single_ms) / 64, min(single_ms), max(single_ms)))
