@@ -395,9 +395,12 @@ typedef struct {
     void* out_dev;              /* as for vr_render */
 } vr_request;
 
-/* Render `count` requests (up to 4096; any mix of cubes, sizes, modes) in one
- * persistent launch on hip_stream.  Each image equals what the request gives
- * when rendered alone in a batch of one.  Optional per-request stats as in
+/* Render `count` requests (up to 4096; any mix of cubes, sizes, modes) on
+ * hip_stream: one persistent launch per class of requests present (a class is
+ * a (mode, storage, interpolation) triple, each with its own specialised
+ * kernel), the requests of a class taken in order, each request's tiles most
+ * expensive first.  Each image equals what the request gives when rendered
+ * alone in a batch of one.  Optional per-request stats as in
  * vr_render (the call then waits).  This is the one-GPU form of the paper's
  * scheduler, which maps rendering tasks onto the available GPUs (Fig. 1
  * caption; Sec. 3.1 process step 2).  Errors as for vr_render, per request

@@ -140,6 +140,37 @@ def test_served_images_match_renderer_and_reference(env):
                         clip=wl.clip_k)
 
 
+def test_new_skip_key_first_use_across_slots(env):
+    """The first requests for a (cube, transfer function, clip) key that has no
+    skip mask yet, split into tile ranges over three inflight slots (separate
+    streams), read the mask only once it is built: the served images equal the
+    same views rendered with skipping off, bit for bit."""
+    r, specs, vols, cubes, tf = env
+    s = specs[1]
+    cams = [synth.orbit_camera(s.nx, s.ny, s.nz, 0.4 + 1.7 * i, 0.3 - 0.2 * i) for i in range(3)]
+    modes = ["ea", "mip", "ea"]
+    clip = 3.37  # used by no other test: its skip mask does not exist yet
+    outs = [r.output(512, 512, m) for m in modes]
+    for o in outs:
+        o.fill_(math.nan)
+    reqs = [r.request(cubes[1], c, 512, 512, o, mode=m, clip=clip) for c, o, m in zip(cams, outs, modes)]
+    r.server_start(max_batch_requests=8, max_batch_tiles=64, max_inflight=3, use_graphs=0)
+    try:
+        tickets = [r.submit(q) for q in reqs]
+        for t in tickets:
+            assert r.wait(t, timeout_s=60) >= 0
+    finally:
+        r.server_stop()
+    for c, o, m in zip(cams, outs, modes):
+        served = to_np(o)
+        assert not np.isnan(served).any()
+        r.set_camera(c)
+        r.set_noise_clip(clip, 1.0)
+        plain = to_np(r.render(cubes[1], 512, 512, mode=m, use_skip=False))
+        r.set_noise_clip(3.0, 1.0)
+        assert np.array_equal(served.view(np.uint32), plain.view(np.uint32)), m
+
+
 def test_server_state_errors(env):
     from paper_1001_2049_amd import vr
     r, specs, vols, cubes, tf = env
