@@ -949,16 +949,27 @@ __device__ __forceinline__ bool tile_march(const DevReq& R, const Ray& ray, cons
             const int lr = div_small(lane, unp, inv_np);
             const uint64_t xo = chunk_off(s, lane - lr * unp);
             const uint64_t brow = (uint64_t)R.cube.bx * bstride;  // bytes of a row of bricks
+            auto zpart = [&](int iz) -> uint64_t {
+                const int gz = min(lo2 + iz, N[2] - 1);
+                const int bzl = min(gz >> 5, R.cube.bz_hi - 1);  // plane 32 of a layer: its apron
+                return (uint64_t)R.cube.pool + (uint64_t)bzl * layer +
+                       (uint32_t)slot_z<DT>(gz - 32 * bzl, R.cube.xch) * ELEM;
+            };
+            // z parts of this wave's planes wv + 4k, one per lane k, read back
+            // with readlane (for boxes of at most 256 planes)
+            const bool ztab = u2 <= VR_NWAVE * 64;
+            const uint64_t zv = ztab && wv + VR_NWAVE * lane < u2 ? zpart(wv + VR_NWAVE * lane) : 0ull;
+            const uint32_t zv_lo = (uint32_t)zv, zv_hi = (uint32_t)(zv >> 32);
             for (int y0 = 0; y0 < u1; y0 += rw) {
                 const int gy = min(lo1 + y0 + lr, N[1] - 1);
                 uint64_t yx = (uint64_t)(gy >> 5) * brow + (uint32_t)slot_y<DT>(gy & 31, R.cube.xch) * ELEM + xo;
                 asm volatile("" : "+v"(yx));  // one register pair, not re-summed per plane
                 const bool on = lr < rw && y0 + lr < u1;
-                for (int iz = wv; iz < u2; iz += VR_NWAVE) {
-                    const int gz = min(lo2 + iz, N[2] - 1);
-                    const int bzl = min(gz >> 5, R.cube.bz_hi - 1);  // plane 32 of a layer: its apron
-                    const uint8_t* zp = R.cube.pool + (uint64_t)bzl * layer +
-                                        (uint32_t)slot_z<DT>(gz - 32 * bzl, R.cube.xch) * ELEM;
+                for (int iz = wv, k = 0; iz < u2; iz += VR_NWAVE, ++k) {
+                    const uint64_t zp =
+                        ztab ? ((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)zv_hi, k) << 32) |
+                                   (uint32_t)__builtin_amdgcn_readlane((int)zv_lo, k)
+                             : zpart(iz);
                     if (on)
                         __builtin_amdgcn_global_load_lds((const void*)(zp + yx),
                                                          (__attribute__((address_space(3))) void*)(ubuf + iz * upb + y0 * unp * 16),
