@@ -16,10 +16,10 @@
 //                 most expensive tiles out first.
 //
 // The render kernels themselves live in vr_render.h and are instantiated in
-// vr_render_<mode>_<storage>.hip (one image per launch; a 256-thread
-// workgroup renders a 16x16 pixel tile, each 64-lane wave an 8x8 sub-tile,
-// two workgroups per compute unit)
-// and vr_render_batch.hip (a persistent grid over many requests).
+// vr_render_<mode>_<storage>.hip: k_render (one image per launch; a
+// 256-thread workgroup renders a 16x16 pixel tile, each 64-lane wave an 8x8
+// sub-tile, two workgroups per compute unit) and k_render_batch (a persistent
+// grid over the requests of one batch class).
 #include <hip/hip_runtime.h>
 #include <math.h>
 #include <stdint.h>
