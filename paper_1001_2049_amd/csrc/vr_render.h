@@ -517,17 +517,14 @@ __device__ __forceinline__ int wave_max(int v) {
 }
 
 // Voxel index and weights of a position in box-local coordinates: clamped to
-// [0, hi] (the cube's last voxel on the upper side; below 0 only in the half
-// voxel outside a cube face, as the box never starts below a sample away from
-// the faces), so truncation is the floor.  Trilinear at q = N - 1 takes the
-// last voxel with weight 0 (its +1 neighbour is the edge-clamped apron).
-// CLAMP = false where every sample of the slab is known to lie in [0, hi],
-// which makes the clamp the identity.
-template <int INTERP, bool CLAMP = true>
+// [0, hi] (the cube's last voxel on the upper side; the box never starts below
+// a sample), so truncation is the floor.  Trilinear at q = N - 1 takes the last
+// voxel with weight 0 (its +1 neighbour is the edge-clamped apron).
+template <int INTERP>
 __device__ __forceinline__ void floor_idx(const float p[3], const float hi[3], int i[3], float w[3]) {
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
-        const float q = CLAMP ? __builtin_amdgcn_fmed3f(p[a], 0.0f, hi[a]) : p[a];
+        const float q = __builtin_amdgcn_fmed3f(p[a], 0.0f, hi[a]);
         if (INTERP == 1) {
             w[a] = __builtin_amdgcn_fractf(q);
             i[a] = (int)q;
@@ -583,7 +580,6 @@ struct Slab {
     int boff;     // byte offset of the box in the LDS box area
     int late;     // copied only after the previous slab is sampled (it or the
                   // previous slab takes both buffers)
-    int inner;    // every sample of the slab lies in [lo, N - 1] on each axis
 };
 
 template <bool B>
@@ -619,9 +615,6 @@ __device__ __forceinline__ Slab slab_box(int z0, int S, const Corners& cr, const
     int lo[3], hi[3];
     lo[M] = max(max(z0 - 1, zmin - 1), CL[M]);
     hi[M] = min(min(z0 + S, zmax + 1), CH[M]);
-    // no sample of the slab needs the clamp of floor_idx (margins far above
-    // the rounding of the sample positions)
-    bool inner = za - 0.01f >= (float)lo[M] && zb + 0.01f <= (float)(N[M] - 1);
 #pragma unroll
     for (int q = 0; q < 2; ++q) {
         const int a = q == 0 ? A1 : A2;
@@ -638,7 +631,6 @@ __device__ __forceinline__ Slab slab_box(int z0, int S, const Corners& cr, const
         // the sliver [-1/2, 0) still reads voxel 0 (and [N - 1, N - 1/2] voxel N - 1)
         lo[a] = max((int)floorf(fminf(mn, (float)(N[a] - 1)) - 0.01f), CL[a]);
         hi[a] = min((int)floorf(fmaxf(mx, 0.0f) + 0.01f), CH[a]);
-        inner = inner && mn - 0.01f >= (float)lo[a] && mx + 0.01f <= (float)(N[a] - 1);
     }
     bool empty = false;
 #pragma unroll
@@ -653,7 +645,6 @@ __device__ __forceinline__ Slab slab_box(int z0, int S, const Corners& cr, const
     s.big = 0;
     s.boff = 0;
     s.late = 0;
-    s.inner = inner ? 1 : 0;
     s.elems = empty ? 0 : box_plane<M, CV>(s.np, s.dim[1]) * s.dim[2];
     return s;
 }
@@ -1063,14 +1054,14 @@ __device__ __forceinline__ bool tile_march(const DevReq& R, const Ray& ray, cons
                 }
                 // samples are taken two at a time so that the second one's box
                 // reads are in flight while the first one is classified
-                auto value = [&](auto fetch, int j, bool last, auto clampc) {
+                auto value = [&](auto fetch, int j, bool last) {
                     const float jf = (float)j + (last ? ray.last_adj : 0.0f);
                     const float p[3] = {__builtin_fmaf(jf, ray.dd[0], A[0]),
                                         __builtin_fmaf(jf, ray.dd[1], A[1]),
                                         __builtin_fmaf(jf, ray.dd[2], A[2])};
                     int i[3];
                     float w[3];
-                    floor_idx<INTERP, decltype(clampc)::value>(p, ch, i, w);
+                    floor_idx<INTERP>(p, ch, i, w);
                     return fetch(i, w);
                 };
                 // Finer skip where under a quarter of the box's cells are
@@ -1133,7 +1124,7 @@ __device__ __forceinline__ bool tile_march(const DevReq& R, const Ray& ray, cons
                         }
                     return t > acc.m;
                 };
-                auto run = [&](auto fetch, auto fetch2, auto chunked, auto clampc) {
+                auto run = [&](auto fetch, auto fetch2, auto chunked) {
                     const int jl = ray.n - 1 - ks;  // index of the ray's last sample in this slab, if any
                     int j = 0;
                     for (; j + 1 < cnt_s; j += 2) {
@@ -1154,8 +1145,8 @@ __device__ __forceinline__ bool tile_march(const DevReq& R, const Ray& ray, cons
                                                  __builtin_fmaf(jb, ray.dd[2], A[2])};
                             int ia[3], ib[3];
                             float wa[3], wb[3];
-                            floor_idx<INTERP, decltype(clampc)::value>(pa, ch, ia, wa);
-                            floor_idx<INTERP, decltype(clampc)::value>(pb, ch, ib, wb);
+                            floor_idx<INTERP>(pa, ch, ia, wa);
+                            floor_idx<INTERP>(pb, ch, ib, wb);
                             fetch2(ia, wa, ib, wb, v0, v1);
                         }
                         if (MODE == 1) {
@@ -1167,7 +1158,7 @@ __device__ __forceinline__ bool tile_march(const DevReq& R, const Ray& ray, cons
                         }
                     }
                     if (j < cnt_s && !stopped) {
-                        const float v = value(fetch, j, j == jl, clampc);
+                        const float v = value(fetch, j, j == jl);
                         ++nexec;
                         if (MODE == 1) {
                             acc.m = fmaxf(acc.m, v);
@@ -1214,11 +1205,9 @@ __device__ __forceinline__ bool tile_march(const DevReq& R, const Ray& ray, cons
                         vb = trilerp(cb[0], cb[1], cb[2], cb[3], cb[4], cb[5], cb[6], cb[7], wb[0], wb[1], wb[2]);
                     };
                     if (fine)
-                        run(fetch, fetch2, BoolC<true>(), BoolC<true>());
-                    else if (s0.inner)
-                        run(fetch, fetch2, BoolC<false>(), BoolC<false>());
+                        run(fetch, fetch2, BoolC<true>());
                     else
-                        run(fetch, fetch2, BoolC<false>(), BoolC<true>());
+                        run(fetch, fetch2, BoolC<false>());
                 } else {
                     auto fetch = [&](const int* i, const float* w) {
                         return pool_value<DT, INTERP>(R.cube, s0.lo[0] + i[0], s0.lo[1] + i[1],
@@ -1230,9 +1219,9 @@ __device__ __forceinline__ bool tile_march(const DevReq& R, const Ray& ray, cons
                         vb = fetch(ib, wb);
                     };
                     if (fine)
-                        run(fetch, fetch2, BoolC<true>(), BoolC<true>());
+                        run(fetch, fetch2, BoolC<true>());
                     else
-                        run(fetch, fetch2, BoolC<false>(), BoolC<true>());
+                        run(fetch, fetch2, BoolC<false>());
                 }
             }
         }
