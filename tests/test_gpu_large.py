@@ -36,6 +36,15 @@ def large():
     synth.cube_gpu(spec, vals)
     r = Renderer(0)
     cube = r.upload(vals, "f16")
+    # compulsory bytes of a view that sees the whole cube: the FP16 voxels of
+    # the 8^3 cells holding a value at or above the clip (no other cell can
+    # contribute), counted on the float32 values, 256 planes at a time
+    active_cells = 0
+    with torch.no_grad():
+        for z0 in range(0, spec.nz, 256):
+            cm = torch.nn.functional.max_pool3d(vals[z0:z0 + 256].reshape(1, 1, -1, spec.ny, spec.nx), 8)
+            active_cells += int((cm >= wl.clip_k * spec.sigma).sum().item())
+            del cm
     codes = np.empty((spec.nz, spec.ny, spec.nx), dtype=np.uint16)
     for z0 in range(0, spec.nz, 256):
         codes[z0:z0 + 256] = vals[z0:z0 + 256].half().cpu().numpy().view(np.uint16)
@@ -44,7 +53,7 @@ def large():
     tf = synth.ramp_tf(256, wl.kappa_max)
     r.set_transfer_function(tf, wl.v0, wl.v1)
     r.set_noise_clip(wl.clip_k, 1.0)
-    yield wl, r, cube, codes, tf
+    yield wl, r, cube, codes, tf, active_cells
     r.close()
     torch.cuda.empty_cache()
 
@@ -52,7 +61,7 @@ def large():
 @pytest.mark.parametrize("mode", ["ea", "mip"])
 def test_large_cube_sampled_pixels(large, mode):
     import torch
-    wl, r, cube, codes, tf = large
+    wl, r, cube, codes, tf, active_cells = large
     W = H = wl.width
     cam = orbit64(wl.cube, 0, W)
     r.set_camera(cam)
@@ -70,6 +79,11 @@ def test_large_cube_sampled_pixels(large, mode):
                            clip=wl.clip_k * wl.cube.sigma)
     record("large f16 2048 %s sampled" % mode, info)
     print("large %s stats=%s" % (mode, st))
+    ncells = (wl.cube.nx // 8) * (wl.cube.ny // 8) * (wl.cube.nz // 8)
+    compulsory = active_cells * 512 * 2 + W * H * (16 if mode == "ea" else 4)
+    print("large %s: %d of %d cells active (%.1f %%), compulsory %.2f GB, %.0f GB/s = %.3f of 8 TB/s"
+          % (mode, active_cells, ncells, 100.0 * active_cells / ncells, compulsory / 1e9,
+             compulsory / (st["kernel_ms"] * 1e-3) / 1e9, compulsory / (st["kernel_ms"] * 1e-3) / 8e12))
     assert st["cells_skipped"] > 0 and st["samples_exec"] < st["samples_nominal"]
 
 
@@ -77,7 +91,7 @@ def test_large_orbit_batch_equals_single(large):
     """The 64-view orbit in one persistent launch and as 64 single launches on
     the same views: every view bit-identical, both timed with HIP events."""
     import torch
-    wl, r, cube, codes, tf = large
+    wl, r, cube, codes, tf, _ = large
     W = H = wl.width
     outs = [r.output(W, H, "ea") for _ in range(64)]
     reqs = [r.request(cube, orbit64(wl.cube, i, W), W, H, outs[i], mode="ea", clip=wl.clip_k)
