@@ -264,6 +264,25 @@ def test_batch_equals_single(R, tiny, tiny_cube):
     torch.cuda.synchronize()
 
 
+def test_batch_request_beyond_one_ordering_run(R, tiny, tiny_cube):
+    """A batched request of 32768 tiles (more than one workgroup orders at
+    once, so its tiles are ordered in two runs) beside a small request of
+    another class: both images equal their single renders bit for bit."""
+    import torch
+    wl, vol, tf = tiny
+    cam = synth.orbit_camera(64, 64, 128, 0.7, 0.35)
+    set_state(R, wl, tf, cam)
+    big = R.output(4096, 2048, "ea")
+    small = R.output(96, 80, "mip")
+    R.render_batch([R.request(tiny_cube, cam, 4096, 2048, big, mode="ea", clip=wl.clip_k),
+                    R.request(tiny_cube, cam, 96, 80, small, mode="mip", clip=wl.clip_k)])
+    single_big = to_np(R.render(tiny_cube, 4096, 2048, mode="ea"))
+    single_small = to_np(R.render(tiny_cube, 96, 80, mode="mip"))
+    assert np.array_equal(to_np(big).view(np.uint32), single_big.view(np.uint32))
+    assert np.array_equal(to_np(small).view(np.uint32), single_small.view(np.uint32))
+    torch.cuda.synchronize()
+
+
 def test_stats_count_nominal_samples(R, tiny, tiny_cube):
     wl, vol, tf = tiny
     cam = synth.orbit_camera(64, 64, 128, 2.2, 0.6)
