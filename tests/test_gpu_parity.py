@@ -406,6 +406,31 @@ def test_large_transfer_function_parity(R, tiny, tiny_cube):
     assert np.array_equal(img.view(np.uint32), to_np(out).view(np.uint32))
 
 
+def test_batch_mixing_transfer_function_sizes(R, tiny, tiny_cube):
+    """One batch with a 256-row and a 4096-row transfer function (the larger
+    table fixes the LDS split of the whole launch, so the small one's slabs
+    get smaller box buffers): each image equals its single render bit for
+    bit."""
+    import torch
+    wl, vol, _ = tiny
+    small_tf = R.tf_create(synth.ramp_tf(256, wl.kappa_max), wl.v0, wl.v1)
+    big_tf = R.tf_create(synth.ramp_tf(4096, wl.kappa_max), wl.v0, wl.v1)
+    try:
+        cams = [synth.orbit_camera(64, 64, 128, 0.4, 0.3), synth.orbit_camera(64, 64, 128, 2.5, -0.2)]
+        outs = [R.output(160, 120, "ea") for _ in cams]
+        R.render_batch([R.request(tiny_cube, cams[0], 160, 120, outs[0], mode="ea", clip=wl.clip_k, tf=small_tf),
+                        R.request(tiny_cube, cams[1], 160, 120, outs[1], mode="ea", clip=wl.clip_k, tf=big_tf)])
+        batch = [to_np(o).copy() for o in outs]
+        for tfid, cam, b in zip((small_tf, big_tf), cams, batch):
+            single = R.output(160, 120, "ea")
+            R.render_batch([R.request(tiny_cube, cam, 160, 120, single, mode="ea", clip=wl.clip_k, tf=tfid)])
+            assert np.array_equal(b.view(np.uint32), to_np(single).view(np.uint32))
+        torch.cuda.synchronize()
+    finally:
+        R.tf_release(small_tf)
+        R.tf_release(big_tf)
+
+
 @pytest.mark.parametrize("mode", ["ea", "mip"])
 def test_rays_grazing_the_low_faces(R, mode):
     """Rays that cross a cube only within half a voxel of its low x face
