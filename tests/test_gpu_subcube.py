@@ -43,7 +43,7 @@ def windows(n, cuts):
 
 
 @pytest.mark.parametrize("axis,cuts,cam_kind", [(2, (32, 64, 100), "below"), (2, (37, 90), "orbit"),
-                                                (0, (20, 41), "orbit")])
+                                                (0, (20, 41), "orbit"), (1, (1, 31, 63), "orbit")])
 @pytest.mark.parametrize("mode", ["ea", "mip"])
 def test_partials_and_composite(scene, axis, cuts, cam_kind, mode):
     r, spec, vol, cube, tf = scene
