@@ -234,6 +234,26 @@ def serving_leg(n_requests=2000, n_warm=200, loads=(0.5, 0.7, 0.9), seed=4242):
     return res
 
 
+def copy_bandwidth_gbs(nbytes=1 << 30, reps=5):
+    """Device-to-device copy rate of nbytes (read plus write bytes per second),
+    the stream bandwidth this HBM actually reaches, as a second reference
+    beside the 8 TB/s specification."""
+    import torch
+    x = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+    y = torch.empty_like(x)
+    y.copy_(x)
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(reps):
+        y.copy_(x)
+    b.record()
+    torch.cuda.synchronize()
+    gbs = 2.0 * nbytes * reps / (a.elapsed_time(b) * 1e-3) / 1e9
+    del x, y
+    torch.cuda.empty_cache()
+    return gbs
+
+
 def kernel_source_digest():
     """SHA-256 over the render kernels' sources, in a fixed order."""
     import hashlib
@@ -433,6 +453,7 @@ def main():
     hbm_achieved = alg_bytes / frame_s / 1e9
     kernel_name = "k_render<%s,%s,trilinear>" % (args.mode, args.storage)
     traffic = measured_traffic(kernel_name, W)
+    copy_gbs = copy_bandwidth_gbs()
 
     res = {
         "metric": "Gsamples/s (nominal samples per second), 1024x1024 view of 512x512x1024 cube",
@@ -457,6 +478,7 @@ def main():
             "mode": args.mode,
             "samples_per_frame": float(np.mean(nominal)),
             "executed_samples_per_frame": float(samples_exec / args.steps),
+            "executed_gsamples_per_s": round(samples_exec / wall / 1e9, 3),
             "kernel_ms_mean": round(avg_ms, 4),
             "kernel_ms_median": round(float(np.median(kernel_ms)), 4),
             "kernel_ms_p90": round(float(np.percentile(kernel_ms, 90)), 4),
@@ -473,6 +495,9 @@ def main():
             "traffic": traffic,
             "kernel": kernel_name,
             "algorithmic_bytes_per_launch": alg_bytes,
+            # the same against the device-to-device copy rate measured in this run
+            "copy_gbs": round(copy_gbs, 1),
+            "frac_of_copy": round(hbm_achieved / copy_gbs, 4),
         },
         # vector-ALU issue (wave instructions x 64 lanes, from committed SQ counters)
         "valu_roofline": measured_valu(kernel_name, W, samples / args.steps, avg_ms),

@@ -10,6 +10,8 @@ float32 values and rounds them itself.  Sampled pixels are compared with the
 FP64 reference at the float32 tolerance (arithmetic check on decoded values),
 and batch members with their single renders bit for bit."""
 import math
+import os
+import time
 
 import numpy as np
 import pytest
@@ -70,8 +72,15 @@ def test_large_cube_sampled_pixels(large, mode):
     got_img = img.cpu().numpy()
     px = synth.pixel_subset(777, W, H, 300)
     got = got_img[px[:, 1], px[:, 0]]
+    t0 = time.perf_counter()
     ref = ref_render(codes, wl_kwargs(wl, tf), cam, W, H, mode, "trilinear", pixels=px,
-                     vox_dtype=oracle.F16)
+                     vox_dtype=oracle.F16, threads=os.cpu_count())
+    t_ref = time.perf_counter() - t0
+    # the reference on the sampled pixels only: per ray, and extrapolated to
+    # the whole frame (an extrapolation, stated as such)
+    print("large %s: reference %.2f ms per ray on %d threads (%d rays), full frame "
+          "extrapolated %.0f s" % (mode, t_ref * 1e3 / len(px), os.cpu_count(), len(px),
+                                   t_ref / len(px) * W * H), flush=True)
     if mode == "ea":
         info = compare_ea(got, ref["values"], TOL_F32, ref["flags"])
     else:

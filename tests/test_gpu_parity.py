@@ -98,6 +98,31 @@ def test_tiny_ea(R, tiny, tiny_cube, view, ert):
     record("tiny f32 %dx%d %s ea ert%g" % (W, H, view, ert), info)
 
 
+def test_tiny_frame_times(R, tiny, tiny_cube):
+    """Frame times of the tiny workload's z view (256^2) on the GPU (median of
+    the library's own kernel timing over 20 frames) and for the FP64
+    reference on all host threads, for EA and both MIP interpolations."""
+    import os
+    import time
+    wl, vol, tf = tiny
+    W = H = 256
+    cam = synth.axis_camera(64, 64, 128, "z", W, H)
+    set_state(R, wl, tf, cam)
+    for mode, interp in (("ea", "trilinear"), ("mip", "trilinear"), ("mip", "nearest")):
+        ms = []
+        for _ in range(20):
+            _, st = R.render(tiny_cube, W, H, mode=mode, interp=interp, step=wl.step, stats=True)
+            ms.append(st["kernel_ms"])
+        t0 = time.perf_counter()
+        ref = ref_render(vol, wl_kwargs(wl, tf), cam, W, H, mode, interp, threads=os.cpu_count())
+        t_ref = time.perf_counter() - t0
+        nominal = int(ref["n_nominal"].sum())
+        assert st["samples_nominal"] == nominal
+        record("timing tiny f32 256x256 z %s %s" % (mode, interp),
+               {"gpu_ms": float(np.median(ms)), "oracle_ms": t_ref * 1e3, "oracle_threads": os.cpu_count(),
+                "samples_nominal": nominal})
+
+
 def test_tiny_ea_opaque_ert(R, tiny, tiny_cube):
     """A strongly absorbing transfer function: many rays terminate early."""
     wl, vol, _ = tiny
