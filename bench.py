@@ -372,6 +372,75 @@ def variants(r, cube_f32, vol, wl, tf, cams, args):
     return out
 
 
+def features(r, cube_f32, vol, wl, cams):
+    """The rows beyond the plain renderer, timed on the full-size FP32 cube at
+    1024^2 (view 0, HIP events on the launch stream):
+    sub-cubes: the cube split into 8 windows of 128 planes along z
+    (512x512x128 each), one partial per window and their integration,
+    against the whole render, ERT off so both images agree to rounding;
+    noise: per-channel median / MAD over the 1024 channels of 512^2 (cube in
+    device memory) and the scaled upload;
+    progressive: the coarse-to-fine levels 4 .. 0 of one view."""
+    import numpy as np
+    import torch
+    W = H = 1024
+    res = {}
+    stream = torch.cuda.current_stream()
+
+    def timed(fn):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        v = fn()
+        b.record(stream)
+        torch.cuda.synchronize()
+        return a.elapsed_time(b), v
+
+    r.set_camera(cams[0])
+    kw = dict(mode="ea", step=wl.step, ert=2.0)
+    whole = r.output(W, H, "ea")
+    r.render(cube_f32, W, H, out=whole, **kw)
+    whole_ms, _ = timed(lambda: r.render(cube_f32, W, H, out=whole, **kw))
+    nz = wl.cube.nz
+    edges = list(range(0, nz + 1, nz // 8))
+    parts = [r.output(W, H, "ea") for _ in range(8)]
+    comp = r.output(W, H, "ea")
+
+    def split():
+        for k in range(8):
+            r.render_subcube(cube_f32, W, H, 2, edges[k], edges[k + 1], out=parts[k], **kw)
+        return None
+    split()
+    split_ms, _ = timed(split)
+    comp_ms, _ = timed(lambda: r.composite(parts, 2, W, H, mode="ea", out=comp))
+    diff = float((comp - whole).abs().max().item())
+    res["subcube_split8_z"] = {"whole_ms": round(whole_ms, 3), "partials_ms": round(split_ms, 3),
+                               "composite_ms": round(comp_ms, 3),
+                               "max_abs_diff_vs_whole": diff}
+
+    dev = torch.from_numpy(vol).cuda()
+    r.estimate_channel_noise(dev)
+    noise_ms, (med, mad, sig) = timed(lambda: r.estimate_channel_noise(dev))
+    up_ms, c2 = timed(lambda: r.upload_scaled(dev, np.maximum(sig, 1e-6), "f32"))
+    r.release(c2)
+    del dev
+    torch.cuda.empty_cache()
+    res["noise"] = {"channels": int(nz), "estimate_ms": round(noise_ms, 3),
+                    "scaled_upload_ms": round(up_ms, 3),
+                    "sigma_mean": round(float(np.mean(sig)), 4)}
+
+    out = r.output(W, H, "ea")
+    levels = []
+    for _ in range(6):
+        info = r.render_progressive(cube_f32, W, H, out, 0.01, max_level=4, mode="ea",
+                                    step=wl.step, ert=wl.ert)
+        if info["converged"]:
+            break
+        levels.append({"level": info["level"], "ms": round(info["ms"], 3),
+                       "samples": int(info["samples_nominal"])})
+    res["progressive"] = levels
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -386,6 +455,8 @@ def main():
     ap.add_argument("--serving-requests", type=int, default=2000)
     ap.add_argument("--serving-warmup", type=int, default=200)
     ap.add_argument("--no-variants", action="store_true")
+    ap.add_argument("--no-features", action="store_true",
+                    help="skip the sub-cube, noise and progressive timings (also off with --no-variants)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only (--gpus %d requested); the renderer has no "
@@ -507,6 +578,10 @@ def main():
     if not args.no_variants and args.storage == "f32" and W == 1024 and args.mode == "ea":
         log("configuration variants")
         res["variants"] = variants(r, cube, vol, wl, tf, cams, args)
+    if (not args.no_features and not args.no_variants and args.storage == "f32" and W == 1024
+            and args.mode == "ea"):
+        log("sub-cubes, noise estimation, progressive levels")
+        res["features"] = features(r, cube, vol, wl, cams)
     if not args.no_cpu_baseline:
         log("timing the CPU reference")
         res["cpu_baseline"] = cpu_baseline(vol, tf, wl, cams, W, H, args.mode)

@@ -1586,7 +1586,7 @@ static vr_status render_streamed(Ctx* c, Cube* cu, Tf* tf, const vr_render_param
         R.win_lo = z_lo == 0 ? -__builtin_huge_valf() : (float)z_lo - 0.5f;
         R.win_hi = z_hi == cu->nz ? __builtin_huge_valf() : (float)z_hi - 0.5f;
         R.win_vlo = std::max(0, z_lo - 1);
-        R.win_vhi = (int)std::min<int64_t>(cu->nz - 1, z_hi);
+        R.win_vhi = z_hi;  // the last sub-cube's samples reach the top face: floor index nz - 1
         R.partial = 1;
         pp[(size_t)k] = (const float*)((uint8_t*)parts.ptr + img * k);
         st = ensure_order(c, R.tiles_x * R.tiles_y, s);
@@ -1698,7 +1698,7 @@ static vr_status render_impl(vr_ctx ctx, vr_cube cube, const vr_render_params* p
             R.win_lo = win->lo == 0 ? -__builtin_huge_valf() : (float)win->lo - 0.5f;
             R.win_hi = win->hi == Na ? __builtin_huge_valf() : (float)win->hi - 0.5f;
             R.win_vlo = std::max(0, win->lo - 1);
-            R.win_vhi = (int)std::min<int64_t>(Na - 1, win->hi);
+            R.win_vhi = win->hi;  // the last window's samples reach the top face: floor index Na - 1
             R.partial = 1;
         }
         DevCounters* dc = nullptr;

@@ -93,6 +93,30 @@ def test_partials_and_composite(scene, axis, cuts, cam_kind, mode):
     record("subcube composite %s axis%d %s" % (mode, axis, cam_kind), info)
 
 
+def test_top_window_after_mip_renders(scene):
+    """Regression: a window that reaches the cube's top face holds samples up
+    to the face, whose floor index is the last plane; its slab boxes must
+    include that plane's +1 neighbour (the edge copy) rather than read past
+    the box, where LDS left by earlier MIP launches (cell bounds of -inf)
+    turned weight-0 corners into NaN samples.  MIP frames are rendered first,
+    then the top window's EA partial is compared with the reference."""
+    r, spec, vol, cube, tf = scene
+    for k in range(4):
+        r.set_camera(synth.orbit_camera(70, 64, 150, 0.7 + 1.3 * k, 0.4 - 0.25 * k))
+        r.render(cube, 180, 140, mode="mip")
+    cam = synth.Camera(eye=(34.0, -40.0, -120.0), target=(34.5, 31.5, 74.5), up=(0.0, 0.0, 1.0),
+                       fovy_deg=40.0)
+    r.set_camera(cam)
+    W, H = 180, 140
+    img, st = r.render_subcube(cube, W, H, 2, 100, 150, mode="ea", ert=2.0, stats=True)
+    got = to_np(img)
+    assert np.isfinite(got).all()
+    kw = dict(tf=tf.astype(np.float64), v0=3.0, v1=30.0, clip=3.0, step=0.5, ert=2.0)
+    ref = ref_render(vol, kw, cam, W, H, "ea", "trilinear", window=(2, 99.5, np.inf))
+    info = compare_ea(got, ref["image"], TOL_F32, ref["flags"])
+    record("subcube ea top window after mip", info)
+
+
 def test_subcube_argument_errors(scene):
     from paper_1001_2049_amd import vr
     r, spec, vol, cube, tf = scene
