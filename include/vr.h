@@ -351,9 +351,19 @@ vr_status vr_composite(vr_ctx ctx, int32_t mode, const float* const* partials, i
  * The paper's thin client turns user interaction into rendering commands and
  * shows the results (Fig. 1 caption; Sec. 3.1, process step 4).  For such an
  * interactive loop, vr_render_progressive renders a view at a level L: an
- * image of ceil(W/2^L) x ceil(H/2^L) pixels with a lattice step 2^L times
- * longer (about 8^L times less work), enlarged to W x H by pixel replication
- * (output pixel (i, j) shows level pixel (i >> L, j >> L)).  On a new view
+ * image of ceil(W/2^L) x ceil(H/2^L) pixels of the level-L cube, enlarged to
+ * W x H by pixel replication (output pixel (i, j) shows level pixel
+ * (i >> L, j >> L)).  The level-L cube averages 2x2x2 blocks of level L - 1
+ * (ceil(n/2) voxels per axis; an odd axis repeats its last voxel), float32,
+ * built on the first call that needs it and kept with the cube (its device
+ * memory counts against the budget and is the first to go when an upload or
+ * admission needs room); level voxel (X, Y, Z) is centred at (2^L X +
+ * (2^L - 1)/2, ...) of the cube, the camera is carried into level
+ * coordinates and the extinction scaled by 2^L, so the level renders the same
+ * rays through the same medium at 1/8^L of the samples.  Where the level-L
+ * cube cannot be used (a streamed cube, an axis below two voxels at that
+ * level, no room in the budget) the level renders the full cube with a
+ * lattice step 2^L times longer instead, and level_cube reports 0.  On a new view
  * (cube, parameters, camera, transfer function, clip or out_dev changed since
  * the previous call) it takes the finest level whose time, predicted from the
  * device time per sample measured on earlier calls, fits budget_ms (the
@@ -369,6 +379,7 @@ typedef struct {
     float ms;                   /* device time of this call (render and enlargement) */
     float predicted_ms;         /* predicted time of the level rendered */
     uint64_t samples_nominal;   /* lattice samples of the level rendered */
+    int32_t level_cube;         /* 1: rendered from the level-L cube; 0: full cube */
 } vr_progressive_info;
 
 vr_status vr_render_progressive(vr_ctx ctx, vr_cube cube, const vr_render_params* params,

@@ -20,7 +20,7 @@ LIB = os.path.join(HERE, "libvr.so")
 SOURCES = ["vr_render_ea_f32.hip", "vr_render_ea_f16.hip",
            "vr_render_ea_bf16.hip", "vr_render_mip_f32.hip", "vr_render_mip_f16.hip",
            "vr_render_mip_bf16.hip", "vr_kernels.hip", "vr_noise.hip", "vr_capi.cpp",
-           "vr_server.cpp", "vr_noalloc.cpp", "vr_subcube.hip"]
+           "vr_server.cpp", "vr_noalloc.cpp", "vr_subcube.hip", "vr_mip.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

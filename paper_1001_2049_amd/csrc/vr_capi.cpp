@@ -766,12 +766,19 @@ static vr_status make_tf(Ctx* c, const float* rgbk, int32_t n, float v0, float v
     return VR_OK;
 }
 
-static vr_status release_tf(Ctx* c, Tf* t) {
+// Free a table's device memory once every queued use of it has completed.
+static vr_status free_tf_device(Ctx* c, Tf* t) {
     vr_status st = t->uses.sync();
     if (st != VR_OK) return st;
     t->uses.destroy();
     dev_free(c, t->dev_rows, false);
     dev_free(c, t->dev_kpos, false);
+    return VR_OK;
+}
+
+static vr_status release_tf(Ctx* c, Tf* t) {
+    vr_status st = free_tf_device(c, t);
+    if (st != VR_OK) return st;
     c->tfs.erase(t->id);
     return VR_OK;
 }
@@ -779,6 +786,11 @@ static vr_status release_tf(Ctx* c, Tf* t) {
 // Free a cube's device memory (pool, statistics, skip masks) once every
 // queued use of it has completed.
 static vr_status drop_device(Ctx* c, Cube* cube) {
+    for (auto& lv : cube->levels) {
+        vr_status st = drop_device(c, lv.get());
+        if (st != VR_OK) return st;
+    }
+    cube->levels.clear();
     vr_status st = cube->uses.sync();
     for (auto& m : cube->masks)
         if (st == VR_OK) st = m.uses.sync();
@@ -909,6 +921,26 @@ static vr_status cube_fill(Ctx* c, Cube* cube, const void* src, int src_dtype, i
 static vr_status make_room(Ctx* c, uint64_t need, const Cube* self, bool may_wait,
                            const std::vector<Cube*>& keep) {
     while (c->budget && c->used + need > c->budget) {
+        // the progressive loop's coarse levels go before any cube
+        Cube* lv_owner = nullptr;
+        for (auto& kv : c->cubes) {
+            Cube* o = kv.second.get();
+            if (o->levels.empty()) continue;
+            bool idle = true;
+            for (auto& lv : o->levels) idle = idle && lv->uses.done();
+            if (idle || may_wait) {
+                lv_owner = o;
+                break;
+            }
+        }
+        if (lv_owner) {
+            for (auto& lv : lv_owner->levels) {
+                vr_status st = drop_device(c, lv.get());
+                if (st != VR_OK) return st;
+            }
+            lv_owner->levels.clear();
+            continue;
+        }
         Cube* victim = nullptr;
         bool waiting = false;  // some candidate is idle but for work in flight
         for (auto& kv : c->cubes) {
@@ -1108,6 +1140,8 @@ vr_status vr_destroy(vr_ctx ctx) {
             std::vector<Tf*> ts;
             for (auto& kv : c->tfs) ts.push_back(kv.second.get());
             for (Tf* t : ts) release_tf(c, t);
+            for (auto& kv : c->prog.level_tfs) free_tf_device(c, kv.second.get());
+            c->prog.level_tfs.clear();
             dev_free(c, c->counters, false);
             dev_free(c, c->order, false);
             dev_free(c, c->ohist, false);
@@ -1635,6 +1669,67 @@ struct SubWindow {
     int axis, lo, hi;
 };
 
+// One image of a resident, non-streamed cube with the given camera and transfer
+// function (the context's clip), optionally restricted to a sub-cube window.
+static vr_status render_one(Ctx* c, Cube* cu, Tf* tf, const vr_camera& cam,
+                            const vr_render_params& p, void* out_dev, hipStream_t s, vr_stats* stats,
+                            const SubWindow* win) {
+    vr_status st = VR_OK;
+    DevReq R;
+    MaskEntry* me = nullptr;
+    c->launch_stamp = c->mask_stamp;
+    st = build_request(c, cu, tf, c->clip, cam, p, out_dev, s, R, &me);
+    if (st != VR_OK) return st;
+    if (win) {
+        const int64_t Na = win->axis == 0 ? cu->nx : (win->axis == 1 ? cu->ny : cu->nz);
+        if (win->lo < 0 || win->hi > Na || win->lo >= win->hi) {
+            set_error("sub-cube planes must satisfy 0 <= lo < hi <= the axis size");
+            return VR_EINVAL;
+        }
+        R.win_axis = win->axis;
+        R.win_lo = win->lo == 0 ? -__builtin_huge_valf() : (float)win->lo - 0.5f;
+        R.win_hi = win->hi == Na ? __builtin_huge_valf() : (float)win->hi - 0.5f;
+        R.win_vlo = std::max(0, win->lo - 1);
+        R.win_vhi = win->hi;  // the last window's samples reach the top face: floor index Na - 1
+        R.partial = 1;
+    }
+    DevCounters* dc = nullptr;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (stats) {
+        st = ensure_counters(c, 1);
+        if (st != VR_OK) return st;
+        dc = (DevCounters*)c->counters.ptr;
+        st = hip_check(hipMemsetAsync(dc, 0, sizeof(DevCounters), s), "hipMemsetAsync");
+        if (st != VR_OK) return st;
+        st = hip_check(hipEventCreate(&e0), "hipEventCreate");
+        if (st == VR_OK) st = hip_check(hipEventCreate(&e1), "hipEventCreate");
+        if (st == VR_OK) st = hip_check(hipEventRecord(e0, s), "hipEventRecord");
+        if (st != VR_OK) return st;
+    }
+    st = ensure_order(c, R.tiles_x * R.tiles_y, s);
+    if (st != VR_OK) return st;
+    st = hip_check(vr_launch_render(R, (int*)c->order.ptr, (unsigned*)c->ohist.ptr, dc, s),
+                   "render launch");
+    if (st == VR_OK) st = hip_check(hipEventRecord(c->order_done, s), "hipEventRecord");
+    if (st != VR_OK) return st;
+    st = mark_use(c, cu, tf, me, s);
+    if (st != VR_OK) return st;
+    if (stats) {
+        st = hip_check(hipEventRecord(e1, s), "hipEventRecord");
+        if (st == VR_OK) st = hip_check(hipEventSynchronize(e1), "render");
+        float ms = 0.0f;
+        if (st == VR_OK) st = hip_check(hipEventElapsedTime(&ms, e0, e1), "hipEventElapsedTime");
+        DevCounters h;
+        if (st == VR_OK)
+            st = hip_check(hipMemcpy(&h, dc, sizeof(h), hipMemcpyDeviceToHost), "hipMemcpy");
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        if (st != VR_OK) return st;
+        fill_stats(h, ms, stats);
+    }
+    return VR_OK;
+}
+
 static vr_status render_impl(vr_ctx ctx, vr_cube cube, const vr_render_params* params, void* out_dev,
                              void* hip_stream, vr_stats* stats, const SubWindow* win) {
     if (!ctx) {
@@ -1683,59 +1778,7 @@ static vr_status render_impl(vr_ctx ctx, vr_cube cube, const vr_render_params* p
             }
             return render_streamed(c, cu, tf, *params, out_dev, s, stats);
         }
-        DevReq R;
-        MaskEntry* me = nullptr;
-        c->launch_stamp = c->mask_stamp;
-        st = build_request(c, cu, tf, c->clip, c->camera, *params, out_dev, s, R, &me);
-        if (st != VR_OK) return st;
-        if (win) {
-            const int64_t Na = win->axis == 0 ? cu->nx : (win->axis == 1 ? cu->ny : cu->nz);
-            if (win->lo < 0 || win->hi > Na || win->lo >= win->hi) {
-                set_error("sub-cube planes must satisfy 0 <= lo < hi <= the axis size");
-                return VR_EINVAL;
-            }
-            R.win_axis = win->axis;
-            R.win_lo = win->lo == 0 ? -__builtin_huge_valf() : (float)win->lo - 0.5f;
-            R.win_hi = win->hi == Na ? __builtin_huge_valf() : (float)win->hi - 0.5f;
-            R.win_vlo = std::max(0, win->lo - 1);
-            R.win_vhi = win->hi;  // the last window's samples reach the top face: floor index Na - 1
-            R.partial = 1;
-        }
-        DevCounters* dc = nullptr;
-        hipEvent_t e0 = nullptr, e1 = nullptr;
-        if (stats) {
-            st = ensure_counters(c, 1);
-            if (st != VR_OK) return st;
-            dc = (DevCounters*)c->counters.ptr;
-            st = hip_check(hipMemsetAsync(dc, 0, sizeof(DevCounters), s), "hipMemsetAsync");
-            if (st != VR_OK) return st;
-            st = hip_check(hipEventCreate(&e0), "hipEventCreate");
-            if (st == VR_OK) st = hip_check(hipEventCreate(&e1), "hipEventCreate");
-            if (st == VR_OK) st = hip_check(hipEventRecord(e0, s), "hipEventRecord");
-            if (st != VR_OK) return st;
-        }
-        st = ensure_order(c, R.tiles_x * R.tiles_y, s);
-        if (st != VR_OK) return st;
-        st = hip_check(vr_launch_render(R, (int*)c->order.ptr, (unsigned*)c->ohist.ptr, dc, s),
-                       "render launch");
-        if (st == VR_OK) st = hip_check(hipEventRecord(c->order_done, s), "hipEventRecord");
-        if (st != VR_OK) return st;
-        st = mark_use(c, cu, tf, me, s);
-        if (st != VR_OK) return st;
-        if (stats) {
-            st = hip_check(hipEventRecord(e1, s), "hipEventRecord");
-            if (st == VR_OK) st = hip_check(hipEventSynchronize(e1), "render");
-            float ms = 0.0f;
-            if (st == VR_OK) st = hip_check(hipEventElapsedTime(&ms, e0, e1), "hipEventElapsedTime");
-            DevCounters h;
-            if (st == VR_OK)
-                st = hip_check(hipMemcpy(&h, dc, sizeof(h), hipMemcpyDeviceToHost), "hipMemcpy");
-            (void)hipEventDestroy(e0);
-            (void)hipEventDestroy(e1);
-            if (st != VR_OK) return st;
-            fill_stats(h, ms, stats);
-        }
-        return VR_OK;
+        return render_one(c, cu, tf, c->camera, *params, out_dev, s, stats, win);
     });
 }
 
@@ -1791,6 +1834,138 @@ vr_status vr_composite(vr_ctx ctx, int32_t mode, const float* const* partials, i
                                              (float*)out_dev, (hipStream_t)hip_stream),
                          "composite launch");
     });
+}
+
+// ---- coarse levels of the progressive loop -----------------------------------
+// Level L of a cube averages 2x2x2 blocks of level L - 1 (ceil(n/2) voxels
+// per axis, the last voxel of an odd axis standing in for the missing half),
+// stored as float32 in the cube's stored units.  A level-L voxel (X, Y, Z) is
+// centred at full-resolution position 2^L X + (2^L - 1)/2, so the camera is
+// carried into level coordinates by p -> (p - (2^L - 1)/2) / 2^L, and one level
+// voxel is 2^L full-resolution lengths, so the transfer function's extinction
+// is scaled by 2^L (an exact power-of-two scaling of every row).
+
+// The next coarser level of a resident cube (or level), built on stream s.
+static vr_status build_level(Ctx* c, const Cube* src, std::unique_ptr<Cube>& out, hipStream_t s) {
+    std::unique_ptr<Cube> lv(new Cube());
+    vr_status st = cube_geometry(lv.get(), (src->nx + 1) / 2, (src->ny + 1) / 2, (src->nz + 1) / 2,
+                                 VR_F32, src->sigma);
+    if (st != VR_OK) return st;
+    const uint64_t pool_bytes = (uint64_t)lv->nslots * lv->stride;
+    const uint64_t stat_bytes = (uint64_t)lv->nslots * 2 * VR_CELLS_PER_BRICK * 4;
+    if (c->budget && c->used + alloc_size(pool_bytes) + alloc_size(stat_bytes) > c->budget)
+        return VR_OK;  // does not fit the budget: no level (out stays empty)
+    st = dev_alloc(c, lv->pool, pool_bytes, true);
+    if (st == VR_OK) st = dev_alloc(c, lv->cellmm, stat_bytes, true);
+    const int64_t plane = lv->nx * lv->ny;
+    const int64_t zs = std::min<int64_t>(lv->nz, 2 * VR_SLOT_ZP);  // a brick layer's planes
+    DevBuf stage;
+    if (st == VR_OK) st = dev_alloc(c, stage, (uint64_t)(plane * zs) * 4, false);
+    DevCube dc{};
+    dc.pool = (const uint8_t*)src->pool.ptr;
+    dc.stride = src->stride;
+    dc.nx = (int)src->nx;
+    dc.ny = (int)src->ny;
+    dc.nz = (int)src->nz;
+    dc.bx = src->Bx;
+    dc.by = src->By;
+    dc.bz = src->Bz;
+    dc.dtype = src->storage;
+    dc.xch = src->xch;
+    dc.bz_hi = src->Bz;
+    for (int bz = 0; bz < lv->Bz && st == VR_OK; ++bz) {
+        const int64_t z0 = (int64_t)bz * VR_BRICK;
+        const int64_t z1 = std::min<int64_t>(z0 + 2 * VR_SLOT_ZP, lv->nz);
+        st = hip_check(vr_launch_mip_down(dc, (int)lv->nx, (int)lv->ny, (int)z0, (int)(z1 - z0),
+                                          (float*)stage.ptr, s),
+                       "coarse level launch");
+        // values are already in stored units: divisor 1
+        if (st == VR_OK)
+            st = hip_check(vr_launch_brick_build(0, VR_F32, stage.ptr, lv->nx, lv->ny, lv->nz, z0, bz,
+                                                 lv->Bx, lv->By, (uint8_t*)lv->pool.ptr, lv->stride,
+                                                 lv->xch, (float*)lv->cellmm.ptr, 1.0f, nullptr, s),
+                           "brick build launch");
+    }
+    vr_status st2 = hip_check(hipStreamSynchronize(s), "hipStreamSynchronize");
+    if (st == VR_OK) st = st2;
+    dev_free(c, stage, false);
+    if (st != VR_OK) {
+        dev_free(c, lv->pool, true);
+        dev_free(c, lv->cellmm, true);
+        return st;
+    }
+    lv->resident = true;
+    out = std::move(lv);
+    return VR_OK;
+}
+
+static vr_camera level_camera(const vr_camera& cam, int L) {
+    const double k = (double)(1 << L), off = 0.5 * (k - 1.0);
+    vr_camera o = cam;
+    for (int a = 0; a < 3; ++a) {
+        o.eye[a] = (cam.eye[a] - off) / k;
+        o.target[a] = (cam.target[a] - off) / k;
+    }
+    o.ortho_w = cam.ortho_w / k;
+    o.ortho_h = cam.ortho_h / k;
+    return o;
+}
+
+// Level L of cube cu and the transfer function to render it with (*lc stays
+// NULL where the level cannot be used: a streamed cube, an axis of fewer than
+// two voxels at that level, a level that does not fit the budget, or an
+// extinction that would overflow when scaled).
+static vr_status level_view(Ctx* c, Cube* cu, int L, Tf* tf, hipStream_t s, Cube** lc, Tf** ltf) {
+    *lc = nullptr;
+    *ltf = nullptr;
+    vr_status st = ensure_resident(c, cu, s, true, {});
+    if (st != VR_OK) return st;
+    if (cu->streamed) return VR_OK;
+    int64_t n[3] = {cu->nx, cu->ny, cu->nz};
+    for (int l = 0; l < L; ++l)
+        for (auto& v : n) v = (v + 1) / 2;
+    if (n[0] < 2 || n[1] < 2 || n[2] < 2) return VR_OK;
+    if (tf) {
+        auto key = std::make_pair(tf->version, L);
+        auto it = c->prog.level_tfs.find(key);
+        if (it == c->prog.level_tfs.end()) {
+            std::vector<float> rows = tf->rows;
+            for (int i = 0; i < tf->n; ++i) {
+                rows[4 * (size_t)i + 3] *= (float)(1 << L);
+                if (!std::isfinite(rows[4 * (size_t)i + 3])) return VR_OK;
+            }
+            // tables of earlier transfer functions are no longer needed
+            for (auto jt = c->prog.level_tfs.begin(); jt != c->prog.level_tfs.end();) {
+                if (jt->first.first != tf->version) {
+                    st = free_tf_device(c, jt->second.get());
+                    if (st != VR_OK) return st;
+                    jt = c->prog.level_tfs.erase(jt);
+                } else {
+                    ++jt;
+                }
+            }
+            Tf* t = nullptr;
+            st = make_tf(c, rows.data(), tf->n, tf->v0, tf->v1, &t);
+            if (st != VR_OK) return st;
+            std::unique_ptr<Tf> own = std::move(c->tfs[t->id]);  // internal: no handle
+            c->tfs.erase(t->id);
+            it = c->prog.level_tfs.emplace(key, std::move(own)).first;
+        }
+        *ltf = it->second.get();
+    }
+    while ((int)cu->levels.size() < L) {
+        const Cube* src = cu->levels.empty() ? cu : cu->levels.back().get();
+        std::unique_ptr<Cube> lv;
+        st = build_level(c, src, lv, s);
+        if (st != VR_OK) return st;
+        if (!lv) return VR_OK;
+        st = mark_use(c, const_cast<Cube*>(src), nullptr, nullptr, s);
+        if (st != VR_OK) return st;
+        cu->levels.push_back(std::move(lv));
+    }
+    *lc = cu->levels[(size_t)L - 1].get();
+    cu->lru = ++c->lru_clock;
+    return VR_OK;
 }
 
 vr_status vr_render_progressive(vr_ctx ctx, vr_cube cube, const vr_render_params* params,
@@ -1870,8 +2045,19 @@ vr_status vr_render_progressive(vr_ctx ctx, vr_cube cube, const vr_render_params
         vr_render_params lp = *params;
         lp.width = std::max(1, (params->width + (1 << L) - 1) >> L);
         lp.height = std::max(1, (params->height + (1 << L) - 1) >> L);
-        lp.step = params->step * (float)(1 << L);
         hipStream_t s = (hipStream_t)hip_stream;
+        st = hip_check(hipSetDevice(c->device), "hipSetDevice");
+        if (st != VR_OK) return st;
+        // a coarse level renders the averaged cube; where that cannot be used,
+        // the full cube with a lattice step 2^L times longer
+        Cube* lc = nullptr;
+        Tf* ltf = nullptr;
+        if (L > 0) {
+            Tf* tf = params->mode == VR_EA ? find_tf(c, c->current_tf) : nullptr;
+            st = level_view(c, find_cube(c, cube), L, tf, s, &lc, &ltf);
+            if (st != VR_OK) return st;
+        }
+        if (!lc) lp.step = params->step * (float)(1 << L);
         void* target = out_dev;
         if (L > 0) {
             const uint64_t need = (uint64_t)lp.width * lp.height * ch * 4;
@@ -1885,7 +2071,10 @@ vr_status vr_render_progressive(vr_ctx ctx, vr_cube cube, const vr_render_params
             target = P.low.ptr;
         }
         vr_stats rs;
-        st = vr_render(ctx, cube, &lp, target, hip_stream, &rs);
+        if (lc)
+            st = render_one(c, lc, ltf, level_camera(c->camera, L), lp, target, s, &rs, nullptr);
+        else
+            st = vr_render(ctx, cube, &lp, target, hip_stream, &rs);
         if (st != VR_OK) return st;
         float ms = rs.kernel_ms;
         if (L > 0) {
@@ -1919,6 +2108,7 @@ vr_status vr_render_progressive(vr_ctx ctx, vr_cube cube, const vr_render_params
         P.level = L;
         P.valid = true;
         info->level = L;
+        info->level_cube = lc ? 1 : 0;
         info->ms = ms;
         info->samples_nominal = rs.samples_nominal;
         return VR_OK;

@@ -82,6 +82,10 @@ struct Cube {
     void* host_pool = nullptr;      // pinned: every slot, in slot order
     int pins = 0;                   // served requests that have started on it
     uint64_t lru = 0;               // last admission or use, in ctx->lru_clock ticks
+    // Coarse levels for the progressive loop (levels[L - 1]: 2x2x2 block means
+    // of level L - 1, float32), built on demand within the budget and freed
+    // with the cube's device memory or when the budget needs room.
+    std::vector<std::unique_ptr<Cube>> levels;
     uint64_t bytes() const;
     uint64_t need_bytes() const;    // device bytes of its pool and statistics
 };
@@ -156,6 +160,9 @@ struct Ctx {
         uint64_t last_samples = 0;
         DevBuf low;                 // reduced-resolution image of a coarse level
         DevCounters* counters = nullptr;
+        // transfer functions of coarse levels (extinction scaled by 2^L), by
+        // (version of the table they derive from, L)
+        std::map<std::pair<int64_t, int>, std::unique_ptr<Tf>> level_tfs;
     } prog;
 
     // The server is shared with callers blocked in vr_wait / vr_poll, so that a

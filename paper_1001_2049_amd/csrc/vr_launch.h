@@ -65,17 +65,18 @@ hipError_t vr_launch_render(const DevReq& R, int* order, unsigned* hist, DevCoun
 hipError_t vr_launch_batch(const DevReq* reqs, const DevItem* items, const int* hdr, int reqs_grid,
                            unsigned class_mask, DevItem* sorted, unsigned* head, DevCounters* cnt,
                            size_t lds_bytes, int grid, hipStream_t s);
-// reqs_grid: workgroups of the ordering kernel (at least the requests);
-// hist: 256 words.
-hipError_t vr_launch_batch(const DevReq* reqs, const DevItem* items, const int* nitems,
-                           int items_cap, int reqs_grid, DevItem* sorted, unsigned* hist, unsigned* head,
-                           DevCounters* cnt, size_t lds_bytes, int grid, hipStream_t s);
 
 // Nearest-neighbour enlargement of a (W >> L) x (H >> L) image (rounded up)
 // with `ch` floats per pixel to W x H: output pixel (i, j) takes low pixel
 // (i >> L, j >> L).
 hipError_t vr_launch_upsample(const float* low, int wl, int hl, int ch, float* out, int W, int H,
                               int L, hipStream_t s);
+
+// Planes [z0, z0 + planes) of the next coarser level of cube c (2x2x2 block
+// means of its stored values, edge-clamped on odd axes; the coarser cube is
+// ceil(n/2) voxels per axis) into out, float32 [plane][ny2][nx2] (device).
+hipError_t vr_launch_mip_down(const DevCube& c, int nx2, int ny2, int z0, int planes, float* out,
+                              hipStream_t s);
 
 // Sub-cube partial images (count <= VR_MAX_PARTIALS, sub-cubes in increasing
 // plane order along `axis`) combined into one image: EA by front-to-back

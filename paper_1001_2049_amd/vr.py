@@ -91,7 +91,8 @@ class vr_memory_stats(ctypes.Structure):
 
 class vr_progressive_info(ctypes.Structure):
     _fields_ = [("level", ctypes.c_int32), ("converged", ctypes.c_int32), ("ms", ctypes.c_float),
-                ("predicted_ms", ctypes.c_float), ("samples_nominal", ctypes.c_uint64)]
+                ("predicted_ms", ctypes.c_float), ("samples_nominal", ctypes.c_uint64),
+                ("level_cube", ctypes.c_int32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
