@@ -380,10 +380,13 @@ def features(r, cube_f32, vol, wl, cams):
     against the whole render, ERT off so both images agree to rounding;
     noise: per-channel median / MAD over the 1024 channels of 512^2 (cube in
     device memory) and the scaled upload;
+    streamed: the cube registered under half its bricks' bytes, frame time;
     progressive: the first call (which builds the cube's coarse levels), then
     the coarse-to-fine levels 4 .. 0 of another view."""
     import numpy as np
     import torch
+
+    import synth
     W = H = 1024
     res = {}
     stream = torch.cuda.current_stream()
@@ -428,6 +431,36 @@ def features(r, cube_f32, vol, wl, cams):
     res["noise"] = {"channels": int(nz), "estimate_ms": round(noise_ms, 3),
                     "scaled_upload_ms": round(up_ms, 3),
                     "sigma_mean": round(float(np.mean(sig)), 4)}
+
+    # the same cube registered from host memory under a budget of half its
+    # bricks: streamed, each frame uploads the bricks over PCIe as sub-cubes of
+    # brick layers (wall-clock, median of 3; the first frame also bricks the
+    # cube into pinned host memory)
+    from paper_1001_2049_amd import Renderer
+    budget = int(r.info(cube_f32).pool_bytes // 2)
+    rs = Renderer(0, budget_bytes=budget)
+    try:
+        rs.set_transfer_function(synth.ramp_tf(256, wl.kappa_max), wl.v0, wl.v1)
+        rs.set_noise_clip(wl.clip_k, wl.cube.sigma)
+        rs.set_camera(cams[0])
+        sc = rs.register(vol, "f32")
+        simg = rs.output(W, H, "ea")
+
+        def wall(fn):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            fn()
+            torch.cuda.synchronize()
+            return 1e3 * (time.perf_counter() - t0)
+        first = wall(lambda: rs.render(sc, W, H, out=simg, **kw))
+        frames = sorted(wall(lambda: rs.render(sc, W, H, out=simg, **kw)) for _ in range(3))
+        res["streamed"] = {"budget_bytes": budget, "pool_bytes": int(rs.info(sc).pool_bytes),
+                           "first_frame_ms": round(first, 1), "frame_ms": round(frames[1], 2),
+                           "resident_ms": round(whole_ms, 3),
+                           "max_abs_diff_vs_resident": float((simg - whole).abs().max().item())}
+    finally:
+        rs.close()
+    torch.cuda.empty_cache()
 
     # the first call on a cube builds its coarse levels (2x2x2 block means)
     out = r.output(W, H, "ea")

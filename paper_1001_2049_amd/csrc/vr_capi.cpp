@@ -1664,7 +1664,7 @@ static vr_status render_streamed(Ctx* c, Cube* cu, Tf* tf, const vr_render_param
     return st;
 }
 
-// A sub-cube window: voxel planes [lo, hi) along one axis.// A sub-cube window: voxel planes [lo, hi) along one axis.
+// A sub-cube window: voxel planes [lo, hi) along one axis.
 struct SubWindow {
     int axis, lo, hi;
 };
