@@ -205,9 +205,23 @@ vr_status vr_cube_upload(vr_ctx ctx, const void* src, int32_t src_dtype, int32_t
  * then drains the device for it, so no request starves.  This is the one-GPU
  * form of the paper's scheduling of sub-cubes of data larger than a single
  * GPU's memory onto the available GPUs (Sec. 2; Sec. 3.1, process steps 1-2).
- * The caller keeps src unchanged and valid until vr_cube_release.  Errors:
- * VR_EINVAL / VR_EUNSUPPORTED as for vr_cube_upload; VR_ENOMEM if the cube
- * alone needs more device memory than the whole budget. */
+ * A cube whose bricks alone exceed the budget is streamed instead (the
+ * paper's data larger than GPU memory, abstract and Sec. 2): on first use it
+ * is bricked into pinned host memory (the cell statistics stay on the
+ * device), and vr_render renders it as sub-cubes of brick layers uploaded in
+ * turn, two device buffers in flight, each rendered to a partial image on the
+ * whole cube's lattice and integrated front to back (as vr_render_subcube and
+ * vr_composite); early termination then acts within each sub-cube.  The two
+ * buffers stay allocated between frames (they count against the budget and
+ * give way, after coarse levels, when an upload or admission needs room), and
+ * consecutive frames take the sub-cubes in opposite orders so that a frame
+ * starts on the two the frame before left on the device.  Streamed cubes are
+ * rendered by vr_render only (VR_EUNSUPPORTED for batches and served
+ * requests).  The caller keeps src unchanged and valid until
+ * vr_cube_release.  Errors: VR_EINVAL / VR_EUNSUPPORTED as for vr_cube_upload;
+ * VR_ENOMEM if even the statistics and two buffers of two brick layers
+ * exceed the budget (vr_render of a streamed cube: also when the budget would
+ * cut it into more than 64 sub-cubes). */
 vr_status vr_cube_register(vr_ctx ctx, const void* src, int32_t src_dtype, int64_t nx, int64_t ny,
                            int64_t nz, int32_t storage, double sigma_scale, vr_cube* out);
 

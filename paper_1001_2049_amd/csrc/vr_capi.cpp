@@ -806,6 +806,10 @@ static vr_status drop_device(Ctx* c, Cube* cube) {
     cube->masks.clear();
     dev_free(c, cube->pool, true);
     dev_free(c, cube->cellmm, true);
+    for (int q = 0; q < 2; ++q) {
+        dev_free(c, cube->sbuf[q], true);
+        cube->sbuf_sub[q] = -1;
+    }
     cube->resident = false;
     return VR_OK;
 }
@@ -939,6 +943,25 @@ static vr_status make_room(Ctx* c, uint64_t need, const Cube* self, bool may_wai
                 if (st != VR_OK) return st;
             }
             lv_owner->levels.clear();
+            continue;
+        }
+        // then the sub-cube buffers other streamed cubes keep between frames
+        Cube* sb_owner = nullptr;
+        for (auto& kv : c->cubes) {
+            Cube* o = kv.second.get();
+            if (o == self || !o->sbuf[0].ptr || o->pins > 0) continue;
+            if (may_wait || o->uses.done()) {
+                sb_owner = o;
+                break;
+            }
+        }
+        if (sb_owner) {
+            vr_status st = sb_owner->uses.sync();
+            if (st != VR_OK) return st;
+            for (int q = 0; q < 2; ++q) {
+                dev_free(c, sb_owner->sbuf[q], true);
+                sb_owner->sbuf_sub[q] = -1;
+            }
             continue;
         }
         Cube* victim = nullptr;
@@ -1549,10 +1572,12 @@ static vr_status render_streamed(Ctx* c, Cube* cu, Tf* tf, const vr_render_param
                                  hipStream_t s, vr_stats* stats) {
     const uint64_t spl = (uint64_t)cu->Bx * cu->By;
     const uint64_t layer = spl * cu->stride;
-    // room for two sub-cube buffers: idle registered cubes give way
-    vr_status st = make_room(c, 4 * layer, cu, true, {});
+    // room for two sub-cube buffers (counting those this cube already holds):
+    // idle registered cubes give way
+    const uint64_t own = cu->sbuf[0].bytes + cu->sbuf[1].bytes;
+    vr_status st = make_room(c, 4 * layer > own ? 4 * layer - own : 0, cu, true, {});
     if (st != VR_OK) return st;
-    const uint64_t avail = c->budget > c->used ? c->budget - c->used : 0;
+    const uint64_t avail = (c->budget > c->used ? c->budget - c->used : 0) + own;
     const int G = (int)std::min<uint64_t>((uint64_t)cu->Bz, avail / (2 * layer) - 1);
     if (G < 1) {
         set_error("no room for two streamed sub-cubes within the memory budget");
@@ -1565,7 +1590,8 @@ static vr_status render_streamed(Ctx* c, Cube* cu, Tf* tf, const vr_render_param
     }
     const int ch = p.mode == VR_EA ? 4 : 1;
     const uint64_t img = (uint64_t)p.width * p.height * ch * 4;
-    DevBuf buf[2], parts;
+    DevBuf* buf = cu->sbuf;
+    DevBuf parts;
     hipStream_t up = nullptr;
     hipEvent_t ev_up[2] = {nullptr, nullptr}, ev_done[2] = {nullptr, nullptr}, e0 = nullptr, e1 = nullptr;
     DevCounters* dc = nullptr;
@@ -1573,14 +1599,21 @@ static vr_status render_streamed(Ctx* c, Cube* cu, Tf* tf, const vr_render_param
     auto cleanup = [&]() {
         if (s) (void)hipStreamSynchronize(s);
         if (up) (void)hipStreamSynchronize(up);
-        for (auto& b : buf) dev_free(c, b, true);
+        if (st != VR_OK) cu->sbuf_sub[0] = cu->sbuf_sub[1] = -1;  // contents unknown
         dev_free(c, parts, false);
         for (auto e : {ev_up[0], ev_up[1], ev_done[0], ev_done[1], e0, e1})
             if (e) (void)hipEventDestroy(e);
         if (up) (void)hipStreamDestroy(up);
     };
-    for (auto& b : buf)
-        if (st == VR_OK) st = dev_alloc(c, b, (uint64_t)(G + 1) * layer, true);
+    if (G != cu->sbuf_G || !buf[0].ptr || !buf[1].ptr) {
+        // buffers of another sub-cube size (or none): start afresh
+        for (int q = 0; q < 2; ++q) {
+            dev_free(c, buf[q], true);
+            cu->sbuf_sub[q] = -1;
+        }
+        cu->sbuf_G = G;
+        for (int q = 0; q < 2 && st == VR_OK; ++q) st = dev_alloc(c, buf[q], (uint64_t)(G + 1) * layer, true);
+    }
     if (st == VR_OK) st = dev_alloc(c, parts, img * nsub, false);
     if (st == VR_OK) st = hip_check(hipStreamCreateWithFlags(&up, hipStreamNonBlocking), "hipStreamCreate");
     for (auto* e : {&ev_up[0], &ev_up[1], &ev_done[0], &ev_done[1]})
@@ -1595,17 +1628,36 @@ static vr_status render_streamed(Ctx* c, Cube* cu, Tf* tf, const vr_render_param
     }
     if (st == VR_OK) st = hip_check(hipEventRecord(e0, s), "hipEventRecord");
     MaskEntry* me = nullptr;
-    for (int k = 0; k < nsub && st == VR_OK; ++k) {
+    // sub-cubes in alternating order from frame to frame; each goes to the
+    // buffer that already holds it, else to the one the previous sub-cube did
+    // not use (at the start: the one not holding the next sub-cube)
+    const bool rev = cu->sbuf_rev;
+    int q_prev = -1;
+    bool read_here[2] = {false, false};  // a render of this frame reads the buffer
+    for (int i = 0; i < nsub && st == VR_OK; ++i) {
+        const int k = rev ? nsub - 1 - i : i;
         const int b0 = k * G, b1 = std::min(b0 + G, cu->Bz), l0 = std::max(0, b0 - 1);
-        const int q = k & 1;
-        // the buffer was last read by the render of sub-cube k - 2
-        if (k >= 2) st = hip_check(hipStreamWaitEvent(up, ev_done[q], 0), "hipStreamWaitEvent");
-        if (st == VR_OK)
-            st = hip_check(hipMemcpyAsync(buf[q].ptr, (const uint8_t*)cu->host_pool + (uint64_t)l0 * layer,
-                                          (size_t)((uint64_t)(b1 - l0) * layer), hipMemcpyHostToDevice, up),
-                           "hipMemcpyAsync");
-        if (st == VR_OK) st = hip_check(hipEventRecord(ev_up[q], up), "hipEventRecord");
-        if (st == VR_OK) st = hip_check(hipStreamWaitEvent(s, ev_up[q], 0), "hipStreamWaitEvent");
+        int q;
+        if (cu->sbuf_sub[0] == k || cu->sbuf_sub[1] == k) {
+            q = cu->sbuf_sub[0] == k ? 0 : 1;
+        } else if (q_prev >= 0) {
+            q = 1 - q_prev;
+        } else {
+            q = cu->sbuf_sub[0] == (rev ? k - 1 : k + 1) ? 1 : 0;
+        }
+        if (cu->sbuf_sub[q] != k) {
+            // the buffer's last reader in this frame must be done with it
+            if (read_here[q]) st = hip_check(hipStreamWaitEvent(up, ev_done[q], 0), "hipStreamWaitEvent");
+            cu->sbuf_sub[q] = -1;
+            if (st == VR_OK)
+                st = hip_check(hipMemcpyAsync(buf[q].ptr, (const uint8_t*)cu->host_pool + (uint64_t)l0 * layer,
+                                              (size_t)((uint64_t)(b1 - l0) * layer), hipMemcpyHostToDevice, up),
+                               "hipMemcpyAsync");
+            if (st == VR_OK) st = hip_check(hipEventRecord(ev_up[q], up), "hipEventRecord");
+            if (st == VR_OK) st = hip_check(hipStreamWaitEvent(s, ev_up[q], 0), "hipStreamWaitEvent");
+            if (st == VR_OK) cu->sbuf_sub[q] = k;
+        }
+        q_prev = q;
         DevReq R;
         if (st == VR_OK) {
             c->launch_stamp = c->mask_stamp;
@@ -1630,7 +1682,9 @@ static vr_status render_streamed(Ctx* c, Cube* cu, Tf* tf, const vr_render_param
                            "render launch");
         if (st == VR_OK) st = hip_check(hipEventRecord(c->order_done, s), "hipEventRecord");
         if (st == VR_OK) st = hip_check(hipEventRecord(ev_done[q], s), "hipEventRecord");
+        read_here[q] = true;
     }
+    cu->sbuf_rev = !rev;
     if (st == VR_OK) {
         DevCam cam;
         camera_setup(c->camera, p.width, p.height, cam);

@@ -80,6 +80,15 @@ struct Cube {
     // groups of brick layers as sub-cubes (vr_render only).
     bool streamed = false;
     void* host_pool = nullptr;      // pinned: every slot, in slot order
+    // Its two device buffers of sub-cubes stay allocated between frames (freed
+    // with its device memory or when the budget needs room), each tagged with
+    // the sub-cube it holds (-1: none) for sub-cubes of sbuf_G brick layers;
+    // frames walk the sub-cubes in alternating order, so a frame starts on the
+    // two sub-cubes the frame before ended with.
+    DevBuf sbuf[2];
+    int sbuf_sub[2] = {-1, -1};
+    int sbuf_G = 0;
+    bool sbuf_rev = false;
     int pins = 0;                   // served requests that have started on it
     uint64_t lru = 0;               // last admission or use, in ctx->lru_clock ticks
     // Coarse levels for the progressive loop (levels[L - 1]: 2x2x2 block means
