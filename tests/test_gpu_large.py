@@ -70,7 +70,7 @@ def test_large_cube_sampled_pixels(large, mode):
     img, st = r.render(cube, W, H, mode=mode, stats=True)
     torch.cuda.synchronize()
     got_img = img.cpu().numpy()
-    px = synth.pixel_subset(777, W, H, 300)
+    px = synth.pixel_subset(777, W, H, 16384)  # a seeded 16384-pixel subset
     got = got_img[px[:, 1], px[:, 0]]
     t0 = time.perf_counter()
     ref = ref_render(codes, wl_kwargs(wl, tf), cam, W, H, mode, "trilinear", pixels=px,
@@ -78,7 +78,7 @@ def test_large_cube_sampled_pixels(large, mode):
     t_ref = time.perf_counter() - t0
     # the reference on the sampled pixels only: per ray, and extrapolated to
     # the whole frame (an extrapolation, stated as such)
-    print("large %s: reference %.2f ms per ray on %d threads (%d rays), full frame "
+    print("large %s: reference %.4f ms per ray on %d threads (%d rays), full frame "
           "extrapolated %.0f s" % (mode, t_ref * 1e3 / len(px), os.cpu_count(), len(px),
                                    t_ref / len(px) * W * H), flush=True)
     if mode == "ea":
