@@ -236,3 +236,41 @@ def test_full_cube_sampled_gate(rend, full_workload, storage, size):
                 report("full arith %s %d view%d %s" % (storage, size, vi, mode), a)
     finally:
         rend.release(cube)
+
+
+def test_full_cube_2048_whole_frame(rend, full_workload):
+    """One whole 2048^2 EA frame of the full-size cube stored as FP16 against
+    the reference on every pixel: on the decoded codes (the renderer's own
+    arithmetic, float32 tolerance) and on the original float32 values (the
+    storage gate).  The reference's time for the whole frame is reported."""
+    import os
+    import time
+
+    import torch
+    wl, vol, tf = full_workload
+    size = 2048
+    cube = rend.upload(vol, "f16")
+    try:
+        cam = synth.orbit_camera(512, 512, 1024, *synth.orbit_angles(wl.extra["camera_seed"], 1)[0])
+        kw = wl_kwargs(wl, tf)
+        rend.set_transfer_function(tf, wl.v0, wl.v1)
+        rend.set_noise_clip(wl.clip_k, 1.0)
+        rend.set_camera(cam)
+        img = rend.render(cube, size, size, mode="ea")
+        torch.cuda.synchronize()
+        got = img.cpu().numpy().astype(np.float64)
+        t0 = time.perf_counter()
+        dec = ref_render(codes_of(vol, "f16"), kw, cam, size, size, "ea", "trilinear",
+                         vox_dtype=CODES["f16"], threads=os.cpu_count())
+        t_ref = time.perf_counter() - t0
+        ref = ref_render(vol, kw, cam, size, size, "ea", "trilinear", amb_ert=TOL_16, amb_clip=TOL_16,
+                         threads=os.cpu_count())
+        a = compare_ea(got, dec["image"], TOL_F32, dec["flags"])
+        g = compare_ea(got, ref["image"], TOL_16, ref["flags"], max_ambiguous_frac=0.05)
+        a["oracle_s"] = t_ref
+        a["oracle_threads"] = os.cpu_count()
+        a["nominal_samples"] = int(dec["n_nominal"].sum())
+        report("whole frame arith f16 2048 view0 ea", a)
+        report("whole frame gate f16 2048 view0 ea", g)
+    finally:
+        rend.release(cube)
