@@ -120,3 +120,37 @@ def test_scaled_upload_rejects_bad_divisors(R, band):
     with pytest.raises(vr.VRError) as e:
         R.upload_scaled(vol, d)
     assert e.value.status == vr.VR_EINVAL
+
+
+def test_progressive_levels_of_a_scaled_cube(R, band):
+    """A cube stored in units of each channel's noise (the reference's robust
+    sigma as divisors) renders its progressive coarse level as the method on
+    the block means of those normalised values, with the one k-sigma clip."""
+    import torch
+    from oracle import levels
+    spec, prof, vol = band
+    _, _, rsig = noise.channel_stats(vol)
+    div = noise.scale_divisors(rsig).astype(np.float32)
+    cube = R.upload_scaled(vol, div, "f32")
+    try:
+        # the stored values: each voxel divided by its channel's divisor in float32
+        stored = (vol.astype(np.float32) / div[:, None, None]).astype(np.float32)
+        tf = synth.ramp_tf(256, 1.0)
+        R.set_transfer_function(tf, 3.0, 30.0)
+        R.set_noise_clip(3.0, 1.0)
+        cam = synth.orbit_camera(spec.nx, spec.ny, spec.nz, 0.8, 0.35)
+        R.set_camera(cam)
+        W, H = 150, 130
+        out = R.output(W, H, "ea")
+        info = R.render_progressive(cube, W, H, out, budget_ms=1e-6, max_level=1, mode="ea")
+        assert info["level"] == 1 and info["level_cube"] == 1
+        torch.cuda.synchronize()
+        low = out.cpu().numpy()[::2, ::2]
+        wl, hl = levels.level_size(W, H, 1)
+        kw = dict(tf=levels.level_tf(tf, 1), v0=3.0, v1=30.0, clip=3.0, step=0.5,
+                  ert=float(np.float32(0.99)))
+        ref = ref_render(levels.level_volume(stored, 1), kw, levels.level_camera(cam, 1), wl, hl,
+                         "ea", "trilinear")
+        record("scaled cube progressive level 1", compare_ea(low, ref["image"], TOL_F32, ref["flags"]))
+    finally:
+        R.release(cube)
