@@ -458,6 +458,20 @@ def features(r, cube_f32, vol, wl, cams):
                            "first_frame_ms": round(first, 1), "frame_ms": round(frames[1], 2),
                            "resident_ms": round(whole_ms, 3),
                            "max_abs_diff_vs_resident": float((simg - whole).abs().max().item())}
+        # its progressive loop: the first call builds resident coarse levels
+        # from the pinned bricks, then levels 2, 1 and the streamed level 0
+        pout = rs.output(W, H, "ea")
+        pk = dict(max_level=3, mode="ea", step=wl.step, ert=wl.ert)
+        got = []
+        t_first = wall(lambda: got.append(rs.render_progressive(sc, W, H, pout, 0.01, **pk)))
+        lv = [{"level": got[0]["level"], "ms": round(got[0]["ms"], 3), "level_cube": got[0]["level_cube"],
+               "call_ms_with_level_build": round(t_first, 1)}]
+        for _ in range(4):
+            inf = rs.render_progressive(sc, W, H, pout, 0.01, **pk)
+            if inf["converged"]:
+                break
+            lv.append({"level": inf["level"], "ms": round(inf["ms"], 3), "level_cube": inf["level_cube"]})
+        res["streamed"]["progressive"] = lv
     finally:
         rs.close()
     torch.cuda.empty_cache()

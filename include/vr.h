@@ -213,7 +213,8 @@ vr_status vr_cube_upload(vr_ctx ctx, const void* src, int32_t src_dtype, int32_t
  * whole cube's lattice and integrated front to back (as vr_render_subcube and
  * vr_composite); early termination then acts within each sub-cube.  The two
  * buffers stay allocated between frames (they count against the budget and
- * give way, after coarse levels, when an upload or admission needs room), and
+ * give way, after other cubes' coarse levels, when an upload or admission
+ * needs room, and to this cube's own coarse levels), and
  * consecutive frames take the sub-cubes in opposite orders so that a frame
  * starts on the two the frame before left on the device.  Streamed cubes are
  * rendered by vr_render only (VR_EUNSUPPORTED for batches and served
@@ -374,8 +375,11 @@ vr_status vr_composite(vr_ctx ctx, int32_t mode, const float* const* partials, i
  * admission needs room); level voxel (X, Y, Z) is centred at (2^L X +
  * (2^L - 1)/2, ...) of the cube, the camera is carried into level
  * coordinates and the extinction scaled by 2^L, so the level renders the same
- * rays through the same medium at 1/8^L of the samples.  Where the level-L
- * cube cannot be used (a streamed cube, an axis below two voxels at that
+ * rays through the same medium at 1/8^L of the samples.  A streamed cube
+ * (larger than the budget) gets its level 1 from its pinned bricks, three
+ * brick layers at a time, its sub-cube buffers giving way; its levels stay
+ * while it is rendered, and go when two sub-cubes no longer fit beside them.
+ * Where the level-L cube cannot be used (an axis below two voxels at that
  * level, no room in the budget) the level renders the full cube with a
  * lattice step 2^L times longer instead, and level_cube reports 0.  On a new view
  * (cube, parameters, camera, transfer function, clip or out_dev changed since

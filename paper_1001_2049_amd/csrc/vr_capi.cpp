@@ -925,11 +925,12 @@ static vr_status cube_fill(Ctx* c, Cube* cube, const void* src, int src_dtype, i
 static vr_status make_room(Ctx* c, uint64_t need, const Cube* self, bool may_wait,
                            const std::vector<Cube*>& keep) {
     while (c->budget && c->used + need > c->budget) {
-        // the progressive loop's coarse levels go before any cube
+        // the progressive loop's coarse levels (of cubes other than self) go
+        // before any cube
         Cube* lv_owner = nullptr;
         for (auto& kv : c->cubes) {
             Cube* o = kv.second.get();
-            if (o->levels.empty()) continue;
+            if (o->levels.empty() || o == self) continue;
             bool idle = true;
             for (auto& lv : o->levels) idle = idle && lv->uses.done();
             if (idle || may_wait) {
@@ -1577,6 +1578,14 @@ static vr_status render_streamed(Ctx* c, Cube* cu, Tf* tf, const vr_render_param
     const uint64_t own = cu->sbuf[0].bytes + cu->sbuf[1].bytes;
     vr_status st = make_room(c, 4 * layer > own ? 4 * layer - own : 0, cu, true, {});
     if (st != VR_OK) return st;
+    if ((c->budget > c->used ? c->budget - c->used : 0) + own < 4 * layer && !cu->levels.empty()) {
+        // its coarse levels leave no room for two sub-cubes: they go
+        for (auto& lv : cu->levels) {
+            st = drop_device(c, lv.get());
+            if (st != VR_OK) return st;
+        }
+        cu->levels.clear();
+    }
     const uint64_t avail = (c->budget > c->used ? c->budget - c->used : 0) + own;
     const int G = (int)std::min<uint64_t>((uint64_t)cu->Bz, avail / (2 * layer) - 1);
     if (G < 1) {
@@ -1953,6 +1962,76 @@ static vr_status build_level(Ctx* c, const Cube* src, std::unique_ptr<Cube>& out
     return VR_OK;
 }
 
+// Level 1 of a streamed cube, built from its pinned bricks: a coarse brick
+// layer's 34 planes come from fine planes [64 bz, 64 bz + 68), so three fine
+// brick layers at a time are uploaded and averaged on the device.  The
+// upload buffer counts against the budget while the level is built.
+static vr_status build_level_streamed(Ctx* c, const Cube* src, std::unique_ptr<Cube>& out,
+                                      hipStream_t s) {
+    std::unique_ptr<Cube> lv(new Cube());
+    vr_status st = cube_geometry(lv.get(), (src->nx + 1) / 2, (src->ny + 1) / 2, (src->nz + 1) / 2,
+                                 VR_F32, src->sigma);
+    if (st != VR_OK) return st;
+    const uint64_t layer = (uint64_t)src->Bx * src->By * src->stride;
+    const int nl = std::min(3, src->Bz);
+    const uint64_t pool_bytes = (uint64_t)lv->nslots * lv->stride;
+    const uint64_t stat_bytes = (uint64_t)lv->nslots * 2 * VR_CELLS_PER_BRICK * 4;
+    if (c->budget && c->used + alloc_size(pool_bytes) + alloc_size(stat_bytes) + alloc_size(nl * layer) >
+                         c->budget)
+        return VR_OK;  // does not fit: no level
+    DevBuf fine, stage;
+    st = dev_alloc(c, lv->pool, pool_bytes, true);
+    if (st == VR_OK) st = dev_alloc(c, lv->cellmm, stat_bytes, true);
+    if (st == VR_OK) st = dev_alloc(c, fine, nl * layer, true);
+    const int64_t plane = lv->nx * lv->ny;
+    const int64_t zs = std::min<int64_t>(lv->nz, 2 * VR_SLOT_ZP);
+    if (st == VR_OK) st = dev_alloc(c, stage, (uint64_t)(plane * zs) * 4, false);
+    for (int bz = 0; bz < lv->Bz && st == VR_OK; ++bz) {
+        const int f0 = 2 * bz, f1 = std::min(f0 + nl, src->Bz);  // fine layers [f0, f1)
+        st = hip_check(hipMemcpyAsync(fine.ptr, (const uint8_t*)src->host_pool + (uint64_t)f0 * layer,
+                                      (size_t)((uint64_t)(f1 - f0) * layer), hipMemcpyHostToDevice, s),
+                       "hipMemcpyAsync");
+        DevCube dc{};
+        // the buffer stands for slots f0*Bx*By .. f1*Bx*By - 1 of the whole pool
+        dc.pool = (const uint8_t*)((uintptr_t)fine.ptr - (uintptr_t)((uint64_t)f0 * layer));
+        dc.stride = src->stride;
+        dc.nx = (int)src->nx;
+        dc.ny = (int)src->ny;
+        dc.nz = (int)src->nz;
+        dc.bx = src->Bx;
+        dc.by = src->By;
+        dc.bz = src->Bz;
+        dc.dtype = src->storage;
+        dc.xch = src->xch;
+        dc.bz_hi = f1;
+        const int64_t z0 = (int64_t)bz * VR_BRICK;
+        const int64_t z1 = std::min<int64_t>(z0 + 2 * VR_SLOT_ZP, lv->nz);
+        // coarse planes [z0, z1) read fine planes [2 z0, 2 z1) (clamped to the
+        // cube), all inside fine layers [f0, f1)
+        if (st == VR_OK)
+            st = hip_check(vr_launch_mip_down(dc, (int)lv->nx, (int)lv->ny, (int)z0, (int)(z1 - z0),
+                                              (float*)stage.ptr, s),
+                           "coarse level launch");
+        if (st == VR_OK)
+            st = hip_check(vr_launch_brick_build(0, VR_F32, stage.ptr, lv->nx, lv->ny, lv->nz, z0, bz,
+                                                 lv->Bx, lv->By, (uint8_t*)lv->pool.ptr, lv->stride,
+                                                 lv->xch, (float*)lv->cellmm.ptr, 1.0f, nullptr, s),
+                           "brick build launch");
+    }
+    vr_status st2 = hip_check(hipStreamSynchronize(s), "hipStreamSynchronize");
+    if (st == VR_OK) st = st2;
+    dev_free(c, fine, true);
+    dev_free(c, stage, false);
+    if (st != VR_OK) {
+        dev_free(c, lv->pool, true);
+        dev_free(c, lv->cellmm, true);
+        return st;
+    }
+    lv->resident = true;
+    out = std::move(lv);
+    return VR_OK;
+}
+
 static vr_camera level_camera(const vr_camera& cam, int L) {
     const double k = (double)(1 << L), off = 0.5 * (k - 1.0);
     vr_camera o = cam;
@@ -1974,7 +2053,6 @@ static vr_status level_view(Ctx* c, Cube* cu, int L, Tf* tf, hipStream_t s, Cube
     *ltf = nullptr;
     vr_status st = ensure_resident(c, cu, s, true, {});
     if (st != VR_OK) return st;
-    if (cu->streamed) return VR_OK;
     int64_t n[3] = {cu->nx, cu->ny, cu->nz};
     for (int l = 0; l < L; ++l)
         for (auto& v : n) v = (v + 1) / 2;
@@ -2010,7 +2088,18 @@ static vr_status level_view(Ctx* c, Cube* cu, int L, Tf* tf, hipStream_t s, Cube
     while ((int)cu->levels.size() < L) {
         const Cube* src = cu->levels.empty() ? cu : cu->levels.back().get();
         std::unique_ptr<Cube> lv;
-        st = build_level(c, src, lv, s);
+        if (src == cu && cu->streamed) {
+            // its sub-cube buffers are a cache between frames: they give way
+            st = cu->uses.sync();
+            if (st != VR_OK) return st;
+            for (int q = 0; q < 2; ++q) {
+                dev_free(c, cu->sbuf[q], true);
+                cu->sbuf_sub[q] = -1;
+            }
+            st = build_level_streamed(c, cu, lv, s);
+        } else {
+            st = build_level(c, src, lv, s);
+        }
         if (st != VR_OK) return st;
         if (!lv) return VR_OK;
         st = mark_use(c, const_cast<Cube*>(src), nullptr, nullptr, s);

@@ -114,3 +114,48 @@ def test_streamed_frames_reuse_sub_cubes_and_yield_them():
         assert np.array_equal(again.view(np.uint32), frames[0].view(np.uint32))
     finally:
         r.close()
+
+
+def test_progressive_levels_of_a_streamed_cube():
+    """A cube larger than the budget gets resident coarse levels, built from its
+    pinned bricks: levels 3, 2, 1 are the method on the level-L cube (FP64
+    reference), and level 0 is the streamed full render, bit for bit."""
+    from oracle import levels
+    from paper_1001_2049_amd import Renderer
+    spec = synth.CubeSpec(160, 144, 200, seed=9093, sources=synth.SourcePop(10, 4, 40, True, 1.5, 6, 2, 20))
+    vol = synth.cube(spec)
+    tf = synth.ramp_tf(256, 1.0)
+    cam = synth.orbit_camera(160, 144, 200, 1.3, 0.45)
+    W, H = 180, 150
+    budget = 28 << 20
+    r = Renderer(0, budget_bytes=budget)
+    try:
+        r.set_transfer_function(tf, 3.0, 40.0)
+        r.set_noise_clip(3.0, 1.0)
+        r.set_camera(cam)
+        cube = r.register(vol, "f32")
+        assert r.info(cube).pool_bytes > budget
+        out = r.output(W, H, "ea")
+        kw = dict(v0=3.0, v1=40.0, clip=3.0, step=0.5, ert=float(np.float32(0.99)))
+        seen = []
+        for _ in range(5):
+            info = r.render_progressive(cube, W, H, out, budget_ms=1e-6, max_level=3, mode="ea")
+            if info["converged"]:
+                break
+            assert r.memory_stats()["used_bytes"] <= budget
+            L = info["level"]
+            seen.append(L)
+            got = to_np(out)
+            if L > 0:
+                assert info["level_cube"] == 1, info
+                wl, hl = levels.level_size(W, H, L)
+                low = got[::2 ** L, ::2 ** L]
+                ref = ref_render(levels.level_volume(vol, L), dict(kw, tf=levels.level_tf(tf, L)),
+                                 levels.level_camera(cam, L), wl, hl, "ea", "trilinear")
+                record("streamed progressive level %d" % L, compare_ea(low, ref["image"], TOL_F32, ref["flags"]))
+            else:
+                full = to_np(r.render(cube, W, H, mode="ea"))
+                assert np.array_equal(got.view(np.uint32), full.view(np.uint32))
+        assert seen == [3, 2, 1, 0], seen
+    finally:
+        r.close()
