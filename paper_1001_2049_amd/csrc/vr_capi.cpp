@@ -1965,8 +1965,10 @@ static vr_status build_level(Ctx* c, const Cube* src, std::unique_ptr<Cube>& out
 // Level 1 of a streamed cube, built from its pinned bricks: a coarse brick
 // layer's 34 planes come from fine planes [64 bz, 64 bz + 68), so three fine
 // brick layers at a time are uploaded and averaged on the device.  The
-// upload buffer counts against the budget while the level is built.
-static vr_status build_level_streamed(Ctx* c, const Cube* src, std::unique_ptr<Cube>& out,
+// upload buffer counts against the budget while the level is built.  The
+// cube's sub-cube buffers (a cache between frames) give way to the level,
+// and only if the level then fits.
+static vr_status build_level_streamed(Ctx* c, Cube* src, std::unique_ptr<Cube>& out,
                                       hipStream_t s) {
     std::unique_ptr<Cube> lv(new Cube());
     vr_status st = cube_geometry(lv.get(), (src->nx + 1) / 2, (src->ny + 1) / 2, (src->nz + 1) / 2,
@@ -1976,9 +1978,18 @@ static vr_status build_level_streamed(Ctx* c, const Cube* src, std::unique_ptr<C
     const int nl = std::min(3, src->Bz);
     const uint64_t pool_bytes = (uint64_t)lv->nslots * lv->stride;
     const uint64_t stat_bytes = (uint64_t)lv->nslots * 2 * VR_CELLS_PER_BRICK * 4;
-    if (c->budget && c->used + alloc_size(pool_bytes) + alloc_size(stat_bytes) + alloc_size(nl * layer) >
-                         c->budget)
+    const uint64_t own = src->sbuf[0].bytes + src->sbuf[1].bytes;
+    if (c->budget && c->used - own + alloc_size(pool_bytes) + alloc_size(stat_bytes) +
+                             alloc_size(nl * layer) > c->budget)
         return VR_OK;  // does not fit: no level
+    if (own) {
+        st = src->uses.sync();
+        if (st != VR_OK) return st;
+        for (int q = 0; q < 2; ++q) {
+            dev_free(c, src->sbuf[q], true);
+            src->sbuf_sub[q] = -1;
+        }
+    }
     DevBuf fine, stage;
     st = dev_alloc(c, lv->pool, pool_bytes, true);
     if (st == VR_OK) st = dev_alloc(c, lv->cellmm, stat_bytes, true);
@@ -2089,13 +2100,6 @@ static vr_status level_view(Ctx* c, Cube* cu, int L, Tf* tf, hipStream_t s, Cube
         const Cube* src = cu->levels.empty() ? cu : cu->levels.back().get();
         std::unique_ptr<Cube> lv;
         if (src == cu && cu->streamed) {
-            // its sub-cube buffers are a cache between frames: they give way
-            st = cu->uses.sync();
-            if (st != VR_OK) return st;
-            for (int q = 0; q < 2; ++q) {
-                dev_free(c, cu->sbuf[q], true);
-                cu->sbuf_sub[q] = -1;
-            }
             st = build_level_streamed(c, cu, lv, s);
         } else {
             st = build_level(c, src, lv, s);
