@@ -199,3 +199,28 @@ def test_register_validation_and_memory_stats(L, ctx):
     assert L.vr_get_memory_stats(ctx, ctypes.byref(m)) == vr.VR_OK
     assert m.as_dict() == {k: 0 for k, _ in vr.vr_memory_stats._fields_}
     assert L.vr_get_memory_stats(ctx, None) == vr.VR_EINVAL
+
+
+def test_progressive_and_subcube_validation(L, ctx):
+    """vr_render_progressive and vr_render_subcube reject bad arguments before any
+    device work; a host-only context cannot render.  The progressive info
+    struct matches the header's layout."""
+    assert ctypes.sizeof(vr.vr_progressive_info) == 4 + 4 + 4 + 4 + 8 + 4 + 4
+    p = vr.make_params(64, 48)
+    info = vr.vr_progressive_info()
+    out = ctypes.c_void_p(0x1000)  # never dereferenced: every call below fails first
+    prog = L.vr_render_progressive
+    assert prog(None, 1, ctypes.byref(p), 1.0, 3, out, None, ctypes.byref(info)) == vr.VR_EINVAL
+    assert prog(ctx, 1, ctypes.byref(p), 1.0, 3, out, None, None) == vr.VR_EINVAL
+    assert prog(ctx, 1, ctypes.byref(p), 1.0, 3, None, None, ctypes.byref(info)) == vr.VR_EINVAL
+    assert prog(ctx, 1, ctypes.byref(p), 1.0, 5, out, None, ctypes.byref(info)) == vr.VR_EINVAL
+    assert prog(ctx, 1, ctypes.byref(p), 1.0, -1, out, None, ctypes.byref(info)) == vr.VR_EINVAL
+    assert prog(ctx, 1, ctypes.byref(p), math.nan, 3, out, None, ctypes.byref(info)) == vr.VR_EINVAL
+    bad = vr.make_params(64, 48, step=0.0)
+    assert prog(ctx, 1, ctypes.byref(bad), 1.0, 3, out, None, ctypes.byref(info)) == vr.VR_EINVAL
+    assert prog(ctx, 1, ctypes.byref(p), 1.0, 3, out, None, ctypes.byref(info)) == vr.VR_EDEVICE
+    assert info.level == 0 and info.converged == 0 and info.level_cube == 0
+    sub = L.vr_render_subcube
+    for axis in (-1, 3):
+        assert sub(ctx, 1, ctypes.byref(p), axis, 0, 4, out, None, None) == vr.VR_EINVAL
+    assert sub(ctx, 1, ctypes.byref(bad), 2, 0, 4, out, None, None) == vr.VR_EINVAL
