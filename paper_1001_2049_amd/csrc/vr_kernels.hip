@@ -192,7 +192,9 @@ __global__ __launch_bounds__(VR_BB_WG) void k_cellbits(const uint64_t* __restric
 #define VR_NBUCKET 128
 
 __device__ __forceinline__ int tile_bucket(const DevReq& R, int tile) {
-    // plain float is enough for an estimate
+    // plain float, with the hardware reciprocal and reciprocal square root,
+    // is enough for an estimate (one workgroup orders a whole image, so this
+    // arithmetic is most of the ordering kernel's time)
     const DevCam& C = R.cam;
     const int tx = tile % R.tiles_x, ty = tile / R.tiles_x;
     const float xa = (float)(tx * VR_TW) + 0.5f, xb = (float)min(tx * VR_TW + VR_TW, R.W) - 0.5f;
@@ -214,12 +216,13 @@ __device__ __forceinline__ int tile_bucket(const DevReq& R, int tile) {
                 n2 = __builtin_fmaf(d[a], d[a], n2);
             }
         }
-        const float inv = C.ortho ? 1.0f : 1.0f / __builtin_sqrtf(n2);
+        const float inv = C.ortho ? 1.0f : __builtin_amdgcn_rsqf(n2);
         float t0 = C.ortho ? -VR_INF : 0.0f, t1 = VR_INF;
         for (int a = 0; a < 3; ++a) {
             const float da = d[a] * inv;
             if (da != 0.0f) {
-                const float u = (-0.5f - o[a]) / da, v = (N[a] - 0.5f - o[a]) / da;
+                const float rd = __builtin_amdgcn_rcpf(da);
+                const float u = (-0.5f - o[a]) * rd, v = (N[a] - 0.5f - o[a]) * rd;
                 t0 = fmaxf(t0, fminf(u, v));
                 t1 = fminf(t1, fmaxf(u, v));
             } else if (o[a] < -0.5f || o[a] > N[a] - 0.5f) {
