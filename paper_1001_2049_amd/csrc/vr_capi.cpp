@@ -446,6 +446,41 @@ static vr_status ensure_counters(Ctx* c, int count) {
 
 // Dispatch-order scratch of a single render; a render on another stream waits
 // for the last one that read it.
+// The two order buffers of single renders (and the side stream and events),
+// grown to ntiles; growing waits for the device.
+static vr_status ensure_order2(Ctx* c, int ntiles) {
+    vr_status st = VR_OK;
+    if (!c->order_side) {
+        st = hip_check(hipStreamCreateWithFlags(&c->order_side, hipStreamNonBlocking), "hipStreamCreate");
+        if (st != VR_OK) {
+            c->order_side = nullptr;
+            return st;
+        }
+    }
+    for (hipEvent_t* e : {&c->order2_free[0], &c->order2_free[1], &c->order2_ready})
+        if (!*e) {
+            st = hip_check(hipEventCreateWithFlags(e, hipEventDisableTiming), "hipEventCreate");
+            if (st != VR_OK) {
+                *e = nullptr;
+                return st;
+            }
+        }
+    if (c->order2_cap < ntiles) {
+        st = hip_check(hipDeviceSynchronize(), "hipDeviceSynchronize");
+        if (st != VR_OK) return st;
+        for (int q = 0; q < 2; ++q) dev_free(c, c->order2[q], false);
+        c->order2_cap = 0;
+        c->order2_used[0] = c->order2_used[1] = false;
+        const int cap = std::max(ntiles, 4096);
+        for (int q = 0; q < 2; ++q) {
+            st = dev_alloc(c, c->order2[q], (uint64_t)cap * sizeof(int) + 1024, false);
+            if (st != VR_OK) return st;
+        }
+        c->order2_cap = cap;
+    }
+    return VR_OK;
+}
+
 static vr_status ensure_order(Ctx* c, int ntiles, hipStream_t s) {
     vr_status st = VR_OK;
     if (c->order_cap < ntiles) {
@@ -1169,6 +1204,12 @@ vr_status vr_destroy(vr_ctx ctx) {
             dev_free(c, c->counters, false);
             dev_free(c, c->order, false);
             dev_free(c, c->ohist, false);
+            for (int q = 0; q < 2; ++q) {
+                dev_free(c, c->order2[q], false);
+                if (c->order2_free[q]) (void)hipEventDestroy(c->order2_free[q]);
+            }
+            if (c->order2_ready) (void)hipEventDestroy(c->order2_ready);
+            if (c->order_side) (void)hipStreamDestroy(c->order_side);
             dev_free(c, c->prog.low, false);
             if (c->order_done) (void)hipEventDestroy(c->order_done);
             free_batch_bufs(c, c->batch);
@@ -1769,11 +1810,34 @@ static vr_status render_one(Ctx* c, Cube* cu, Tf* tf, const vr_camera& cam,
         if (st == VR_OK) st = hip_check(hipEventRecord(e0, s), "hipEventRecord");
         if (st != VR_OK) return st;
     }
-    st = ensure_order(c, R.tiles_x * R.tiles_y, s);
+    hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+    st = hip_check(hipStreamIsCapturing(s, &cap), "hipStreamIsCapturing");
     if (st != VR_OK) return st;
-    st = hip_check(vr_launch_render(R, (int*)c->order.ptr, (unsigned*)c->ohist.ptr, dc, s),
-                   "render launch");
-    if (st == VR_OK) st = hip_check(hipEventRecord(c->order_done, s), "hipEventRecord");
+    if (cap != hipStreamCaptureStatusNone) {
+        // under capture everything stays on the caller's stream
+        st = ensure_order(c, R.tiles_x * R.tiles_y, s);
+        if (st != VR_OK) return st;
+        st = hip_check(vr_launch_render(R, (int*)c->order.ptr, (unsigned*)c->ohist.ptr, dc, s),
+                       "render launch");
+        if (st == VR_OK) st = hip_check(hipEventRecord(c->order_done, s), "hipEventRecord");
+    } else {
+        st = ensure_order2(c, R.tiles_x * R.tiles_y);
+        if (st != VR_OK) return st;
+        const int q = c->order2_next;
+        c->order2_next ^= 1;
+        int* ord = (int*)c->order2[q].ptr;
+        unsigned* hist = (unsigned*)(ord + c->order2_cap);
+        // the order needs no earlier work on s, only the end of the render
+        // that last read this buffer
+        if (c->order2_used[q])
+            st = hip_check(hipStreamWaitEvent(c->order_side, c->order2_free[q], 0), "hipStreamWaitEvent");
+        if (st == VR_OK) st = hip_check(vr_launch_order(R, ord, hist, c->order_side), "order launch");
+        if (st == VR_OK) st = hip_check(hipEventRecord(c->order2_ready, c->order_side), "hipEventRecord");
+        if (st == VR_OK) st = hip_check(hipStreamWaitEvent(s, c->order2_ready, 0), "hipStreamWaitEvent");
+        if (st == VR_OK) st = hip_check(vr_launch_render_ordered(R, ord, dc, s), "render launch");
+        if (st == VR_OK) st = hip_check(hipEventRecord(c->order2_free[q], s), "hipEventRecord");
+        if (st == VR_OK) c->order2_used[q] = true;
+    }
     if (st != VR_OK) return st;
     st = mark_use(c, cu, tf, me, s);
     if (st != VR_OK) return st;

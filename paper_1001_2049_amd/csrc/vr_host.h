@@ -157,6 +157,15 @@ struct Ctx {
     DevBuf order, ohist;         // single-render dispatch order and its bucket counts
     int order_cap = 0;
     hipEvent_t order_done = nullptr;  // last render that read `order`
+    // Single renders compute each frame's dispatch order on a side stream into
+    // one of two buffers (cap ints, then 256 histogram words), so that it can
+    // run while the frame before is still rendering.
+    DevBuf order2[2];
+    int order2_cap = 0, order2_next = 0;
+    bool order2_used[2] = {false, false};
+    hipEvent_t order2_free[2] = {nullptr, nullptr};  // last render that read the buffer
+    hipEvent_t order2_ready = nullptr;
+    hipStream_t order_side = nullptr;
     BatchBufs batch;
 
     // progressive (coarse-to-fine) rendering: the view of the last call, the

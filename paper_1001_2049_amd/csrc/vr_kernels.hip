@@ -481,8 +481,7 @@ VR_BATCH_LAUNCHER_DECL(1, 0)
 VR_BATCH_LAUNCHER_DECL(1, 1)
 VR_BATCH_LAUNCHER_DECL(1, 2)
 
-hipError_t vr_launch_render(const DevReq& R, int* order, unsigned* hist, DevCounters* cnt,
-                            hipStream_t s) {
+hipError_t vr_launch_order(const DevReq& R, int* order, unsigned* hist, hipStream_t s) {
     const int n = R.tiles_x * R.tiles_y;
     if (n <= VR_ORDER_FUSED_MAX) {
         hipLaunchKernelGGL(k_order_fused_one, dim3(1), dim3(VR_ORDER_FUSED_WG), 0, s, R, n, order);
@@ -492,8 +491,18 @@ hipError_t vr_launch_render(const DevReq& R, int* order, unsigned* hist, DevCoun
         hipLaunchKernelGGL(k_order_count_one, dim3(ob), dim3(256), 0, s, R, n, hist);
         hipLaunchKernelGGL(k_order_scatter_one, dim3(ob), dim3(256), 0, s, R, n, hist, order);
     }
-    hipError_t e = hipGetLastError();
+    return hipGetLastError();
+}
+
+hipError_t vr_launch_render(const DevReq& R, int* order, unsigned* hist, DevCounters* cnt,
+                            hipStream_t s) {
+    const hipError_t e = vr_launch_order(R, order, hist, s);
     if (e != hipSuccess) return e;
+    return vr_launch_render_ordered(R, order, cnt, s);
+}
+
+hipError_t vr_launch_render_ordered(const DevReq& R, const int* order, DevCounters* cnt,
+                                    hipStream_t s) {
     switch (R.mode * 10 + R.cube.dtype) {
         case 0: return vr_launch_render_0_0(R, order, cnt, s);
         case 1: return vr_launch_render_0_1(R, order, cnt, s);

@@ -53,6 +53,12 @@ hipError_t vr_launch_classify(const float* cell_minmax, uint64_t* mask, uint32_t
 // first.  order: device scratch of tiles_x * tiles_y ints; hist: 256 words.
 hipError_t vr_launch_render(const DevReq& R, int* order, unsigned* hist, DevCounters* cnt,
                             hipStream_t s);
+// The two halves of vr_launch_render: the dispatch order of R's tiles into
+// `order` (it reads only R's camera, image and cube geometry), and the render
+// of R in that order.
+hipError_t vr_launch_order(const DevReq& R, int* order, unsigned* hist, hipStream_t s);
+hipError_t vr_launch_render_ordered(const DevReq& R, const int* order, DevCounters* cnt,
+                                    hipStream_t s);
 
 // Many images in persistent launches over a (request, tile) work list,
 // one launch per batch class present (bit k of class_mask: class k, see
