@@ -170,3 +170,33 @@ def test_large_cube_streamed_under_a_budget(large):
     finally:
         rs.close()
         torch.cuda.empty_cache()
+
+
+def test_large_cube_progressive_levels(large):
+    """The progressive loop on the resident 32 GiB cube: the first call builds
+    its coarse levels (2x2x2 block means on the device) and shows level 3;
+    each further call refines, and level 0 is the full render bit for bit.
+    Level and build times are reported."""
+    import torch
+    wl, r, cube, codes, tf, _ = large
+    W = H = wl.width
+    r.set_camera(orbit64(wl.cube, 5, W))
+    out = r.output(W, H, "ea")
+    seen = []
+    for _ in range(5):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        info = r.render_progressive(cube, W, H, out, budget_ms=1e-6, max_level=3, mode="ea")
+        torch.cuda.synchronize()
+        wall = 1e3 * (time.perf_counter() - t0)
+        if info["converged"]:
+            break
+        seen.append(info["level"])
+        print("large progressive level %d: %.2f ms on the device, %.1f ms for the call, level cube %d"
+              % (info["level"], info["ms"], wall, info["level_cube"]), flush=True)
+        if info["level"] > 0:
+            assert info["level_cube"] == 1
+    assert seen == [3, 2, 1, 0], seen
+    full = r.render(cube, W, H, mode="ea")
+    torch.cuda.synchronize()
+    assert torch.equal(out.view(torch.int32), full.view(torch.int32))
